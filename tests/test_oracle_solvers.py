@@ -1,0 +1,142 @@
+"""Pins of the oracle's CG and of its Algorithm 1 emulation: dense linear
+solves, the free-field FFT solve, the pure-gauge closed form, and the
+failure paths.  CPU only."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import freefield, lowprec, solvers, wilson
+
+
+def rel2(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def test_cg_matches_dense_solve_4x4x4x4():
+    dims = (4, 4, 4, 4)
+    g = synth.rng(0)
+    U = synth.links_haar(dims, g)
+    eta = synth.spinor_gauss(dims, g)
+    m = 0.1
+    M = wilson.dense_matrix(U, m)
+    A = M.conj().T @ M
+    xref = wilson.from_vector(np.linalg.solve(A, wilson.to_vector(eta)), dims)
+    x, info = solvers.cg(solvers.ddagd_operator(U, m), eta, tol=1e-10)
+    assert info["status"] == solvers.OK
+    assert info["true_rel_res"] <= 1e-10
+    kappa = np.linalg.cond(A)
+    assert rel2(x, xref) <= kappa * 2e-10
+
+
+def test_cg_free_field_fft():
+    dims = (4, 2, 6, 8)
+    g = synth.rng(1)
+    eta = synth.spinor_gauss(dims, g)
+    m = 0.2
+    x, info = solvers.cg(solvers.ddagd_operator(synth.links_unit(dims), m), eta, tol=1e-11)
+    assert info["status"] == solvers.OK
+    xref = freefield.solve_ddagd(eta, m)
+    assert rel2(x, xref) < freefield.condition_number(m) * 2e-11
+
+
+def test_cg_pure_gauge_closed_form():
+    # U_mu(n) = Omega(n) Omega(n+mu)^dag makes D[U] = Omega D[1] Omega^dag,
+    # so (D^dag D)^{-1} eta = Omega (D^dag D)_free^{-1} Omega^dag eta.
+    dims = (4, 2, 6, 4)
+    g = synth.rng(2)
+    om = synth.gauge_transform_haar(dims, g)
+    U = synth.links_pure_gauge(om)
+    eta = synth.spinor_gauss(dims, g)
+    m = 0.3
+    x, info = solvers.cg(solvers.ddagd_operator(U, m), eta, tol=1e-11)
+    assert info["status"] == solvers.OK
+    om_dag = np.conj(np.swapaxes(om, -1, -2))
+    xref = synth.gauge_transform_spinor(
+        freefield.solve_ddagd(synth.gauge_transform_spinor(eta, om_dag), m), om)
+    assert rel2(x, xref) < freefield.condition_number(m) * 2e-11
+
+
+def test_cg_fixed_iterations_and_resume():
+    dims = (4, 2, 2, 2)
+    g = synth.rng(4)
+    U = synth.links_haar(dims, g)
+    eta = synth.spinor_gauss(dims, g)
+    op = solvers.ddagd_operator(U, 0.1)
+    x5, info5 = solvers.cg(op, eta, fixed_iters=5)
+    assert info5["iters"] == 5
+    # resuming from x5 converges to the same criterion
+    x, info = solvers.cg(op, eta, tol=1e-10, x0=x5)
+    assert info["status"] == solvers.OK and info["true_rel_res"] <= 1e-10
+
+
+def test_cg_failure_paths():
+    dims = (2, 2, 2, 2)
+    g = synth.rng(5)
+    U = synth.links_haar(dims, g)
+    eta = synth.spinor_gauss(dims, g)
+    op = solvers.ddagd_operator(U, 0.1)
+    # max_iter reached
+    _, info = solvers.cg(op, eta, tol=1e-14, max_iter=1)
+    assert info["status"] == solvers.ENOCONV and info["iters"] == 1
+    # NaN in the source
+    bad = eta.copy()
+    bad[0, 0, 0, 0, 0, 0] = np.nan
+    _, info = solvers.cg(op, bad, tol=1e-10)
+    assert info["status"] == solvers.EBREAKDOWN
+    # a non positive definite operator (shifted far below the spectrum)
+    shifted = lambda v: op(v) - 1e3 * v
+    _, info = solvers.cg(shifted, eta, tol=1e-10)
+    assert info["status"] == solvers.EBREAKDOWN
+
+
+@pytest.mark.parametrize("fmt,delta", [("f32", 1e-3), ("f16s", 0.1), ("bf16s", 0.1), ("f64", 1e-3)])
+def test_mixed_cg_reaches_true_residual(fmt, delta):
+    dims = (4, 2, 6, 2)
+    g = synth.rng(6)
+    U = synth.links_exp(dims, 0.3, g)
+    eta = synth.spinor_gauss(dims, g)
+    m = 0.02
+    x, info = solvers.mixed_cg(U, eta, m, tol=1e-10, inner_fmt=fmt, delta=delta)
+    assert info["status"] == solvers.OK, info
+    # true residual recomputed independently of the solver
+    res = np.linalg.norm((eta - wilson.ddagd(U, x, m)).ravel()) / np.linalg.norm(eta.ravel())
+    assert res <= 1e-10
+    xref, _ = solvers.cg(solvers.ddagd_operator(U, m), eta, tol=1e-12)
+    assert rel2(x, xref) < 1e-5
+
+
+def test_mixed_cg_carried_direction_helps():
+    # The carried search direction (p0 = r0 + beta0 p~) must not cost more
+    # inner iterations than restarting every cycle from p0 = r0.
+    dims = (4, 2, 6, 2)
+    g = synth.rng(6)
+    U = synth.links_exp(dims, 0.3, g)
+    eta = synth.spinor_gauss(dims, g)
+    _, carried = solvers.mixed_cg(U, eta, 0.02, inner_fmt="f32", delta=1e-3)
+    _, plain = solvers.cg(solvers.ddagd_operator(U, 0.02), eta, tol=1e-10)
+    assert carried["iters"] < 1.5 * plain["iters"]
+
+
+def test_lowprec_formats():
+    g = synth.rng(8)
+    v = synth.spinor_gauss((2, 2, 2, 2), g) * 10.0 ** g.uniform(-30, 30, size=(2, 2, 2, 2))[..., None, None]
+    for fmt, eps in (("f32", 2.0 ** -24), ("f16s", 2.0 ** -11), ("bf16s", 2.0 ** -8)):
+        w = lowprec.store(v, fmt)
+        s = lowprec.site_scale(v)[..., None, None]
+        err = np.maximum(np.abs((w - v).real), np.abs((w - v).imag))
+        assert np.all(err <= eps * (s if fmt != "f32" else np.abs(v.real) + np.abs(v.imag)) * 1.0001)
+    # the per-site maximum maps to +-1 exactly
+    w = lowprec.store(v, "f16s")
+    s = lowprec.site_scale(v)
+    m = np.maximum(np.abs(w.real).max(axis=(-1, -2)), np.abs(w.imag).max(axis=(-1, -2)))
+    assert np.allclose(m / s, 1.0, rtol=2 ** -23)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    g = synth.rng(9)
+    x = g.standard_normal(10000) * 10.0 ** g.uniform(-5, 5, 10000)
+    ours = lowprec._round_bf16(x)
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
