@@ -1,0 +1,283 @@
+"""Benchmark of the Wilson-Dirac hot path on one MI355X.
+
+Headline (one JSON line on stdout): float64 Wilson-Dirac application D of
+eq. (1) on the 16^3 x 32 lattice (U = exp(i 0.3 H) links, 18 reals per
+link, m_q = 0.05, seed 0), as algorithmic GB/s.  One step = one full-lattice
+D (both parities) on one of several resident copies of the inputs, rotated so
+that a step never finds its operands in the 256 MB last-level cache: the
+figure is an HBM figure.  Algorithmic bytes per site = 4 links x 144 B + one
+spinor read + one spinor written (960 B in float64, 18-real).
+
+The same line carries the roofline of that kernel (HIP events on the launch
+stream), the CPU oracle timed on a bounded sample of the same workload, and
+"extra" results: 12-real links, the HBM-bound 32^3 x 64 lattice in every
+precision, and CG time-to-1e-10 (float64 vs Algorithm 1 mixed precision).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LLC_BYTES = 256 * 2 ** 20
+FLOPS_PER_SITE = 1464  # paper's count per stencil (Kernel Description)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def site_bytes(prec, link, nrhs=1):
+    """Compulsory HBM bytes per site of one full D: every link once, the input
+    spinor once, the output spinor once (per right-hand side)."""
+    link_b = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[prec] * link * 4
+    spin_b = {"f64": 192, "f32": 96, "f16s": 52, "bf16s": 52}[prec]
+    return link_b + 2 * spin_b * nrhs
+
+
+def gen_inputs(dims, seed=0, eps=0.3, nrhs=None):
+    import synth
+    g = synth.rng(seed)
+    U = synth.links_exp(dims, eps, g)
+    psi = synth.spinor_gauss(dims, g, nrhs=nrhs)
+    return U, psi
+
+
+class Timer:
+    """HIP events on the current (launch) stream."""
+
+    def __init__(self, torch):
+        self.t = torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.t.cuda.synchronize()
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self.b.synchronize()
+        self.ms = self.a.elapsed_time(self.b)
+
+
+def time_dslash(torch, D, dims, prec, link, U, psi, steps, warmup, nrhs=1, m_q=0.05, dagger=False,
+                tune=True):
+    """Average ms of one D application, rotating over enough input copies to
+    defeat the last-level cache.  Returns (ms, copies, launch config)."""
+    op = D.Operator(dims, m_q, prec, link, nrhs)
+    Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    pi = op.pack_spinor(torch.from_numpy(psi).cuda())
+    per_set = op.gauge_bytes() + 2 * op.spinor_bytes()
+    copies = max(1, min(8, math.ceil(2 * LLC_BYTES / per_set) + 1))
+    sets = [(Ui, pi, op.empty_spinor())]
+    for _ in range(copies - 1):
+        sets.append((Ui.clone(), pi.clone(), op.empty_spinor()))
+    if tune and not op.launch_config()["tuned"]:
+        op.autotune(Ui, pi, sets[0][2])
+    for k in range(warmup):
+        u, p, c = sets[k % copies]
+        op.apply(u, p, out=c, dagger=dagger)
+    with Timer(torch) as t:
+        for k in range(steps):
+            u, p, c = sets[k % copies]
+            op.apply(u, p, out=c, dagger=dagger)
+    return t.ms / steps, copies, op.launch_config()
+
+
+def cg_time(torch, D, dims, U, eta, m_q, inner, link=18, tol=1e-10, reps=1):
+    op = D.Operator(dims, m_q, "f64", link)
+    Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    Ul = None
+    if inner != "f64":
+        lo = op.like(prec=inner, link=link if inner == "f32" else 12)
+        Ul = lo.pack_gauge(torch.from_numpy(U).cuda())
+    e = op.pack_spinor(torch.from_numpy(eta).cuda())
+    # one untimed solve (tuning, first-touch), then the timed ones
+    D.cg(op, Ui, e, tol=tol, inner_prec=inner, U_lo=Ul)
+    best = None
+    for _ in range(reps):
+        x = torch.zeros_like(e)
+        with Timer(torch) as t:
+            x, st = D.cg(op, Ui, e, x, tol=tol, inner_prec=inner, U_lo=Ul)
+        r = dict(ms=t.ms, iters=st[0]["iters"], outer=st[0]["outer"], true_rel_res=st[0]["true_rel_res"],
+                 status=st[0]["status"], dslash_hi=st[0]["dslash_hi"], dslash_lo=st[0]["dslash_lo"])
+        if best is None or r["ms"] < best["ms"]:
+            best = r
+    return best
+
+
+def copy_ceiling(torch, gib=1.0, reps=5):
+    """A plain device-to-device copy of known size: the measured bandwidth
+    ceiling, and the reference kernel for scaling the HBM byte counters."""
+    n = int(gib * 2 ** 30)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            dst.copy_(src)
+    ms = t.ms / reps
+    del src, dst
+    return {"bytes_per_copy": 2 * n, "ms": round(ms, 4), "GB/s": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+
+
+def cpu_baseline(dims, U, psi, m_q, budget_s=12.0):
+    """The oracle's D on the same lattice, timed on the host with one BLAS thread."""
+    from oracle import wilson
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        wilson.dslash(U, psi, m_q)  # warm-up
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            wilson.dslash(U, psi, m_q)
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        el = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    V = int(np.prod(dims))
+    gbs = site_bytes("f64", 18) * V * n / el / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} full float64 applications of D on {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
+                      f"({el:.1f} s, NumPy, one thread)",
+            "ms_per_step": round(1e3 * el / n, 2),
+            "host_cpus": os.cpu_count()}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="headline only (no extra sections)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--copy-gib", type=float, default=1.0,
+                    help="size of the plain copy measured as the bandwidth ceiling (0: skip)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); "
+              "this build has no multi-GPU path.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1904_08616_amd import dirac as D
+
+    torch.cuda.set_device(0)
+    dims = (16, 16, 16, 32)
+    V = int(np.prod(dims))
+    m_q = 0.05
+    log("generating 16^3x32 inputs")
+    U, psi = gen_inputs(dims, seed=0)
+
+    copy = copy_ceiling(torch, a.copy_gib) if a.copy_gib > 0 else None
+
+    log("headline: float64 Dslash 16^3x32, 18-real links")
+    ms, copies, cfg = time_dslash(torch, D, dims, "f64", 18, U, psi, a.steps, a.warmup, m_q=m_q)
+    bytes_per = site_bytes("f64", 18) * V
+    gbs = bytes_per / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "Dslash GB/s (% HBM peak); CG time-to-1e-10 residual, mixed vs FP64",
+        "value": round(gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "wilson_dslash_16x16x16x32_f64",
+            "lattice": list(dims),
+            "links": "exp(i*0.3*H), H Gaussian traceless Hermitian, seed 0, 18 reals per link",
+            "source": "complex Gaussian spinor, seed 0",
+            "m_q": m_q,
+            "input_copies_rotated": copies,
+            "launch": cfg,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "k_dslash<F64,F64,18,false,store,1>",
+            "algorithmic_bytes_per_launch": bytes_per,
+            "avg_launch_ms": round(ms, 5),
+            "gflops": round(FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
+        },
+    }
+    extra = {}
+    if copy:
+        extra["copy_ceiling"] = copy
+        line["roofline"]["frac_of_copy"] = round(gbs / copy["GB/s"], 4)
+    if not a.quick:
+        try:
+            ms12, _, cfg12 = time_dslash(torch, D, dims, "f64", 12, U, psi, a.steps, a.warmup, m_q=m_q)
+            b12 = site_bytes("f64", 12) * V
+            extra["dslash_16x16x16x32_f64_link12"] = {
+                "ms": round(ms12, 5), "GB/s": round(b12 / (ms12 * 1e-3) / 1e9, 1),
+                "frac": round(b12 / (ms12 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launch": cfg12}
+            log("CG 16^3x32 float64 vs mixed")
+            eta = psi
+            for inner, link in (("f64", 18), ("f64", 12), ("f32", 12), ("f16s", 12)):
+                extra[f"cg_16x16x16x32_m0.05_{inner}_link{link}"] = cg_time(torch, D, dims, U, eta, m_q, inner,
+                                                                            link=link)
+            big = (32, 32, 32, 64)
+            log("generating 32^3x64 inputs")
+            Ub, pb = gen_inputs(big, seed=0)
+            Vb = int(np.prod(big))
+            for prec, link in (("f64", 18), ("f64", 12), ("f32", 12), ("f16s", 12)):
+                log(f"Dslash 32^3x64 {prec}/{link}")
+                msb, cp, cfgb = time_dslash(torch, D, big, prec, link, Ub, pb, max(20, a.steps // 8), 5,
+                                            m_q=0.02)
+                bb = site_bytes(prec, link) * Vb
+                extra[f"dslash_32x32x32x64_{prec}_link{link}"] = {
+                    "ms": round(msb, 4), "GB/s": round(bb / (msb * 1e-3) / 1e9, 1),
+                    "frac": round(bb / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "GFLOP/s": round(FLOPS_PER_SITE * Vb / (msb * 1e-3) / 1e9, 1), "launch": cfgb}
+            log("CG 32^3x64 m=0.02: float64 vs mixed")
+            for inner, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
+                extra[f"cg_32x32x32x64_m0.02_{inner}_link{link}"] = cg_time(torch, D, big, Ub, pb, 0.02, inner,
+                                                                            link=link)
+            del Ub, pb
+        except Exception as e:  # report, but keep the headline
+            extra["error"] = repr(e)
+    if extra:
+        line["extra"] = extra
+    if not a.no_cpu:
+        log("CPU oracle baseline")
+        U, psi = gen_inputs(dims, seed=0)
+        line["cpu_baseline"] = cpu_baseline(dims, U, psi, m_q)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,250 @@
+/*
+ * dirac.h -- C ABI of libdirac: the Wilson-Dirac operator of eq. (1) and the
+ * conjugate-gradient solve on D^dagger D (Algorithm 1), on hand-written HIP
+ * kernels for AMD gfx950 (MI355X).
+ *
+ * The operator (eq. (1), Introduction):
+ *
+ *   (D psi)(n) = (m_q + 4) psi(n)
+ *              + 1/2 sum_mu [ U_mu(n) P^{-mu} psi(n+mu) + U_mu(n-mu)^dag P^{+mu} psi(n-mu) ]
+ *
+ * with P^{-+mu} = 1 -+ gamma_mu (chiral gamma basis, mu = 0..3 <-> x,y,z,t),
+ * periodic boundaries, hopping sign as printed.
+ *
+ * General rules for every entry point:
+ *   - Pointers are DEVICE pointers owned by the caller unless marked "host".
+ *     The library keeps no reference to them after the call returns (except
+ *     a graph plan, see dirac_multi_plan_create).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued asynchronously on it; only cg_solve, dirac_field_dot,
+ *     dirac_autotune and the plan/graph calls synchronise the stream.
+ *   - Return value: DIRAC_OK (0) or a negative status.  Arguments are
+ *     validated on the host before anything is launched; on error nothing is
+ *     launched and dirac_last_error() describes the problem.  Nothing aborts
+ *     or throws across the ABI.
+ *   - Device buffers must be 256-byte aligned (every hipMalloc / torch CUDA
+ *     allocation is); inputs and outputs of one call must not overlap.
+ *
+ * Canonical (user) layouts, complex128 = two float64 (re, im):
+ *   gauge links U : [Lt][Lz][Ly][Lx][4 (mu)][3][3]  (row-major colour matrix)
+ *   spinor psi    : [nrhs][Lt][Lz][Ly][Lx][4 (spin)][3 (colour)]
+ *   link force F  : same shape as U.
+ * Internal layouts are opaque; their sizes come from dirac_*_bytes.  They
+ * are structure-of-arrays over checkerboard (even-odd) sites, 16-byte
+ * vectors per site component, so neighbouring threads touch neighbouring
+ * addresses.
+ */
+#ifndef DIRAC_H
+#define DIRAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage/arithmetic precision of internal fields.
+ *   F64   : float64 spinors and links, float64 arithmetic.
+ *   F32   : float32 spinors and links, float32 arithmetic.
+ *   F16S  : float16 spinor payload with one float32 scale per site
+ *           (max |real component| of the site), float16 links (unscaled,
+ *           |U_ij| <= 1), float32 arithmetic.
+ *   BF16S : as F16S with bfloat16 payloads.
+ * Every global reduction accumulates in float64 in all precisions. */
+enum { DIRAC_F64 = 0, DIRAC_F32 = 1, DIRAC_F16S = 2, DIRAC_BF16S = 3 };
+
+/* Link storage: the full 3x3 complex matrix (18 reals) or its first two rows
+ * (12 reals) with row 2 = conj(row0 x row1) rebuilt in registers (exact for
+ * SU(3); the paper trades link words for arithmetic in the same way, section
+ * "Larger Lattice Streamed from the DDR Memory").  F16S/BF16S need LINK12. */
+enum { DIRAC_LINK18 = 18, DIRAC_LINK12 = 12 };
+
+enum {
+  DIRAC_OK = 0,
+  DIRAC_EINVAL = -1,       /* bad argument (message in dirac_last_error) */
+  DIRAC_EDEVICE = -2,      /* a HIP call failed */
+  DIRAC_ENOCONV = -3,      /* solver hit max_iter; x holds the last iterate */
+  DIRAC_EBREAKDOWN = -4,   /* NaN/Inf or <p, A p> <= 0 in the solver */
+  DIRAC_EUNSUPPORTED = -5, /* valid but not implemented combination */
+  DIRAC_EWORKSPACE = -6    /* workspace too small */
+};
+
+/* One operator instance: lattice geometry, precision, link storage, number
+ * of right-hand sides and quark mass m_q of eq. (1). */
+typedef struct dirac_op {
+  int32_t L[4];   /* Lx, Ly, Lz, Lt: each even and >= 2, V = product < 2^31 */
+  int32_t prec;   /* DIRAC_F64 / F32 / F16S / BF16S */
+  int32_t link;   /* DIRAC_LINK18 / DIRAC_LINK12 */
+  int32_t nrhs;   /* 1..12 right-hand sides stored one after another */
+  int32_t flags;  /* 0 */
+  double m_q;     /* quark mass, finite */
+} dirac_op;
+
+/* Bytes of one internal spinor buffer holding all nrhs fields, or of one
+ * internal gauge buffer.  Negative status on an invalid op. */
+int64_t dirac_spinor_bytes(const dirac_op* op);
+int64_t dirac_gauge_bytes(const dirac_op* op);
+
+/* Canonical complex128 -> internal (links: round to op->prec and drop row 2
+ * for LINK12; spinors: round, and for F16S/BF16S compute the per-site
+ * scale) and back.  Unpack of a low-precision field returns its exactly
+ * representable complex128 value. */
+int dirac_pack_gauge(const dirac_op* op, const void* U_c128, void* U_int, void* stream);
+int dirac_pack_spinor(const dirac_op* op, const void* psi_c128, void* psi_int, void* stream);
+int dirac_unpack_spinor(const dirac_op* op, const void* psi_int, void* psi_c128, void* stream);
+
+/* Convert an internal spinor buffer between precisions (same geometry and
+ * nrhs).  Rounds to nearest even; F16S/BF16S targets recompute the scale. */
+int dirac_convert_spinor(const dirac_op* op_src, const void* src,
+                         const dirac_op* op_dst, void* dst, void* stream);
+
+/* chi = D psi (eq. (1)), all nrhs fields, each link load shared by the
+ * right-hand sides a thread handles.  U_int, psi_int in op's internal
+ * layout; chi_int receives the result in the same precision. */
+int dirac_apply(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int,
+                void* stream);
+
+/* chi = D^dagger psi = gamma5 D gamma5 psi: eq. (1) with P^{-mu} and P^{+mu}
+ * exchanged (the operator applied at Algorithm 1's D^dagger D products). */
+int dirac_dagger_apply(const dirac_op* op, const void* U_int, const void* psi_int,
+                       void* chi_int, void* stream);
+
+/* chi = D^dagger D psi through tmp (one more internal spinor buffer). */
+int dirac_mdagm_apply(const dirac_op* op, const void* U_int, const void* psi_int, void* tmp_int,
+                      void* chi_int, void* stream);
+
+/* <a, b> = sum conj(a) b over all sites, per right-hand side, accumulated in
+ * float64 with a fixed-order (deterministic) reduction.  out_host receives
+ * nrhs complex values as (re, im) pairs.  Synchronises the stream. */
+int dirac_field_dot(const dirac_op* op, const void* a_int, const void* b_int, double* out_host,
+                    void* stream);
+
+/* y = a x + y on internal fields of one precision, complex scalar a given by
+ * (a_re, a_im), same for every right-hand side. */
+int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x_int, void* y_int,
+                     void* stream);
+
+/* ---------------------------------------------------------------- CG ---- */
+
+/* Solver parameters (Algorithm 1).
+ *   tol         : stop when ||eta - D^dag D x|| / ||eta|| < tol, with the
+ *                 residual recomputed in float64 (never the recursive one).
+ *   max_iter    : cap on the total number of (inner) CG iterations.
+ *   inner_prec  : DIRAC_F64 -> plain float64 CG (inner loop of Algorithm 1
+ *                 run entirely in high precision);
+ *                 DIRAC_F32 / F16S / BF16S -> Algorithm 1: float64 outer
+ *                 loop (true residual, normalisation, solution update),
+ *                 inner CG with that storage and float32 arithmetic.
+ *   inner_delta : inner stop when ||r_inner|| < inner_delta (the inner
+ *                 residual starts at norm 1); <= 0 picks 1e-3 (F32) or
+ *                 0.1 (F16S/BF16S).
+ *   inner_kmax  : cap on one inner solve (<= 0: 10000).
+ *   check_every : iterations launched between host convergence checks
+ *                 (<= 0: automatic).
+ */
+typedef struct cg_params {
+  double tol;
+  int32_t max_iter;
+  int32_t inner_prec;
+  double inner_delta;
+  int32_t inner_kmax;
+  int32_t check_every;
+} cg_params;
+
+/* Per right-hand-side results (host). */
+typedef struct cg_stats {
+  int32_t status;      /* DIRAC_OK, DIRAC_ENOCONV or DIRAC_EBREAKDOWN */
+  int32_t iters;       /* CG iterations (inner iterations for Algorithm 1) */
+  int32_t outer;       /* outer cycles (true-residual recomputations) */
+  int32_t dslash_hi;   /* high-precision D or D^dag applications */
+  int32_t dslash_lo;   /* low-precision D or D^dag applications */
+  int32_t pad;
+  double true_rel_res; /* final ||eta - A x|| / ||eta||, float64 */
+  double seconds;      /* wall time of the whole solve */
+} cg_stats;
+
+/* Bytes of scratch the solve needs for op_hi (which must be DIRAC_F64) and
+ * params.  The caller allocates it (any device allocation). */
+int64_t cg_workspace_bytes(const dirac_op* op_hi, const cg_params* params);
+
+/* Solve D^dagger D x = eta for each of op_hi->nrhs right-hand sides.
+ *   op_hi : DIRAC_F64 operator (LINK18 or LINK12).
+ *   U_hi  : links packed for op_hi.
+ *   U_lo  : links packed for the inner precision (op_hi with prec =
+ *           params->inner_prec and link = DIRAC_LINK12, or op_hi's link for
+ *           F32); NULL when inner_prec == DIRAC_F64.
+ *   eta   : F64 internal source(s); x: F64 internal initial guess on entry
+ *           (a restart / resume point; zero it for x0 = 0), solution on exit.
+ *   stats : host array of nrhs entries.
+ * Returns DIRAC_OK when every right-hand side converged, else the first
+ * non-OK per-RHS status (x still holds each RHS's last iterate).
+ * Synchronises the stream. */
+int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* eta, void* x,
+             void* work, int64_t work_bytes, const cg_params* params, cg_stats* stats,
+             void* stream);
+
+/* ------------------------------------------------------------ gradient ---- */
+
+/* Link gradient of a real loss L through chi = D(U) psi (the backward of
+ * eq. (1) with respect to U), given g = dL/dRe chi + i dL/dIm chi:
+ *
+ *   F_mu(n) = coeff/2 [ sum_alpha g(n)_alpha (P^{-mu} psi(n+mu))_alpha^dag
+ *                     + sum_alpha (P^{+mu} psi(n))_alpha g(n+mu)_alpha^dag ],
+ *
+ * evaluated with half spinors (two colour outer products per term).
+ * g_int, psi_int: internal spinors of op (F64 or F32, nrhs = 1).
+ * F_c128: canonical complex128 [Lt][Lz][Ly][Lx][4][3][3]; written, or added
+ * to when accumulate != 0.  One gather per link, no atomics. */
+int dirac_force(const dirac_op* op, const void* g_int, const void* psi_int, void* F_c128,
+                double coeff, int32_t accumulate, void* stream);
+
+/* --------------------------------------------- batching and autotuning ---- */
+
+/* Apply D (dagger = 0) or D^dagger (dagger = 1) on up to 8 independent
+ * lattices (own geometry, links and m_q; one shared precision and link
+ * storage; nrhs = 1) in ONE persistent kernel launch that walks a work list
+ * of (lattice, tile) pairs.  ops, U, psi, chi are host arrays of n entries. */
+int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U,
+                      const void* const* psi, void* const* chi, int32_t dagger, void* stream);
+
+/* Capture dirac_multi_apply with these arguments into a hipGraph once and
+ * return an opaque plan (host) that replays it with dirac_plan_launch.  The
+ * plan keeps the pointers: the buffers must outlive it. */
+int dirac_multi_plan_create(int32_t n, const dirac_op* ops, const void* const* U,
+                            const void* const* psi, void* const* chi, int32_t dagger,
+                            void* stream, void** plan_out);
+int dirac_plan_launch(void* plan, void* stream);
+int dirac_plan_destroy(void* plan);
+
+/* Time the Dslash launch candidates (threads per block, right-hand sides
+ * per thread, XCD-aware tile order on/off, LDS staging on/off) for this op
+ * on the given buffers with HIP events, and remember the fastest for every
+ * later call with the same (device, geometry, precision, links, nrhs).
+ * chi_int is overwritten.  Synchronises the stream.
+ * If the environment variable DIRAC_TUNE_CACHE names a file, results are
+ * appended there and read back by later processes. */
+int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int,
+                   void* stream);
+
+/* The launch configuration the next dirac_apply with this op will use
+ * (host out-params); tuned != 0 when it came from the autotuner. */
+int dirac_launch_config(const dirac_op* op, int32_t* block_sites, int32_t* rhs_per_thread,
+                        int32_t* xcd_remap, int32_t* lds, int32_t* tuned);
+
+/* Force the launch configuration used for this op (for tests and expert
+ * tuning): block_sites in {64, 128, 256}, rhs_per_thread in 1..4,
+ * xcd_remap 0/1, lds must be 0. */
+int dirac_set_launch_config(const dirac_op* op, int32_t block_sites, int32_t rhs_per_thread,
+                            int32_t xcd_remap, int32_t lds);
+
+/* Description of the last error on the calling host thread ("" if none). */
+const char* dirac_last_error(void);
+
+/* Library version string, e.g. "dirac 0.1 gfx950". */
+const char* dirac_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIRAC_H */

@@ -136,3 +136,37 @@ def to_vector(psi):
 def from_vector(v, dims):
     lx, ly, lz, lt = dims
     return np.asarray(v).reshape(lt, lz, ly, lx, 4, 3)
+
+
+def dslash_at(U, psi, m_q, sites, dagger=False):
+    """(D psi)(n) (or (D^dagger psi)(n)) at the listed sites only.
+
+    ``sites`` is an integer array [k, 4] of coordinates (x, y, z, t).  Each
+    output is gathered from the site and its eight neighbours with explicit
+    periodic index arithmetic (no np.roll), so large lattices can be checked
+    on a sample of sites.  Returns [k, 4, 3].
+    """
+    U = np.asarray(U)
+    psi = np.asarray(psi)
+    lt, lz, ly, lx = U.shape[:4]
+    ext = np.array([lx, ly, lz, lt])
+    s = np.asarray(sites, dtype=np.int64).reshape(-1, 4)
+
+    def at(f, c):
+        return f[c[:, 3], c[:, 2], c[:, 1], c[:, 0]]
+
+    out = (m_q + 4.0) * at(psi, s).astype(np.complex128)
+    for mu in range(4):
+        fw = s.copy()
+        fw[:, mu] = (fw[:, mu] + 1) % ext[mu]
+        bw = s.copy()
+        bw[:, mu] = (bw[:, mu] - 1) % ext[mu]
+        u_here = at(U, s)[:, mu].astype(np.complex128)
+        u_back = at(U, bw)[:, mu].astype(np.complex128)
+        if not dagger:
+            pf, pb = P_MINUS[mu], P_PLUS[mu]
+        else:
+            pf, pb = P_PLUS[mu], P_MINUS[mu]
+        out = out + 0.5 * np.einsum("ij,kab,kjb->kia", pf, u_here, at(psi, fw))
+        out = out + 0.5 * np.einsum("ij,kba,kjb->kia", pb, np.conj(u_back), at(psi, bw))
+    return out

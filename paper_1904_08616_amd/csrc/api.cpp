@@ -1,0 +1,621 @@
+// C ABI of libdirac: argument validation, error reporting, kernel dispatch,
+// launch-configuration cache and autotuner.  See include/dirac.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lib.h"
+
+namespace dirac {
+
+const DslashEntry* dslash_table_f64(int* n);
+const DslashEntry* dslash_table_f32(int* n);
+const DslashEntry* dslash_table_f16(int* n);
+
+namespace {
+thread_local std::string g_error;
+}
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return DIRAC_OK;
+  return set_error(DIRAC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool valid_prec(int p) {
+  return p == DIRAC_F64 || p == DIRAC_F32 || p == DIRAC_F16S || p == DIRAC_BF16S;
+}
+
+int check_op(const dirac_op* op, OpInfo* o, const char* what) {
+  if (op == nullptr) return set_error(DIRAC_EINVAL, "%s: op is NULL", what);
+  int64_t V = 1;
+  for (int d = 0; d < 4; ++d) {
+    if (op->L[d] < 2 || (op->L[d] & 1))
+      return set_error(DIRAC_EINVAL, "%s: every extent must be even and >= 2 (L[%d] = %d)", what, d, op->L[d]);
+    V *= op->L[d];
+    if (V >= (int64_t(1) << 31)) return set_error(DIRAC_EINVAL, "%s: lattice volume must be < 2^31", what);
+  }
+  if (!valid_prec(op->prec)) return set_error(DIRAC_EINVAL, "%s: unknown precision %d", what, op->prec);
+  if (op->link != DIRAC_LINK18 && op->link != DIRAC_LINK12)
+    return set_error(DIRAC_EINVAL, "%s: link must be 18 or 12 (got %d)", what, op->link);
+  if ((op->prec == DIRAC_F16S || op->prec == DIRAC_BF16S) && op->link != DIRAC_LINK12)
+    return set_error(DIRAC_EUNSUPPORTED, "%s: F16S/BF16S need 12-real links", what);
+  if (op->nrhs < 1 || op->nrhs > kMaxRhs)
+    return set_error(DIRAC_EINVAL, "%s: nrhs must be in 1..%d (got %d)", what, kMaxRhs, op->nrhs);
+  if (!std::isfinite(op->m_q)) return set_error(DIRAC_EINVAL, "%s: m_q must be finite", what);
+  if (op->flags != 0) return set_error(DIRAC_EINVAL, "%s: flags must be 0", what);
+  const int64_t fb = spinor_field_bytes(op->prec, V);
+  const int64_t gb = link_bytes(op->prec, op->link) * 4 * V;
+  if (fb >= (int64_t(1) << 32) || gb >= (int64_t(1) << 32))
+    return set_error(DIRAC_EUNSUPPORTED, "%s: one field or the links exceed 4 GiB", what);
+  o->g = make_geom(op->L);
+  o->prec = op->prec;
+  o->link = op->link;
+  o->nrhs = op->nrhs;
+  o->m_q = op->m_q;
+  o->V = V;
+  o->field_bytes = (uint32_t)fb;
+  o->field_stride = align256(fb);
+  o->gauge_bytes = (uint32_t)gb;
+  return DIRAC_OK;
+}
+
+FieldRef field_as(const OpInfo& o, int prec, const void* p) {
+  FieldRef f;
+  f.ptr = (char*)p;
+  f.prec = prec;
+  const int64_t fb = spinor_field_bytes(prec, o.V);
+  f.bytes = (uint32_t)fb;
+  f.stride = align256(fb);
+  return f;
+}
+
+FieldRef field_of(const OpInfo& o, const void* p) { return field_as(o, o.prec, p); }
+
+// ----------------------------------------------------------- dispatch ---
+static std::vector<DslashEntry>& dslash_entries() {
+  static std::vector<DslashEntry> all = [] {
+    std::vector<DslashEntry> v;
+    const DslashEntry* (*tabs[3])(int*) = {dslash_table_f64, dslash_table_f32, dslash_table_f16};
+    for (auto t : tabs) {
+      int n = 0;
+      const DslashEntry* e = t(&n);
+      v.insert(v.end(), e, e + n);
+    }
+    return v;
+  }();
+  return all;
+}
+
+int run_dslash(int pin, int pout, int link, int dag, int epi, const LaunchCfg& c, DslashArgs a,
+               hipStream_t st) {
+  for (const DslashEntry& e : dslash_entries()) {
+    if (e.pin == pin && e.pout == pout && e.link == link && e.dag == dag && e.epi == epi && e.rpt == c.R) {
+      a.remap = c.remap;
+      return hip_status(e.fn(a, c.S, st), "dslash launch");
+    }
+  }
+  return set_error(DIRAC_EUNSUPPORTED, "no Dslash kernel for prec %d->%d link %d dag %d epilogue %d R %d",
+                   pin, pout, link, dag, epi, c.R);
+}
+
+DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out) {
+  DslashArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = o.g;
+  a.U = (const char*)U;
+  a.U_bytes = o.gauge_bytes;
+  a.field_bytes = o.field_bytes;
+  a.out_bytes = o.field_bytes;
+  a.in = (const char*)in;
+  a.in_stride = o.field_stride;
+  a.out = (char*)out;
+  a.out_stride = o.field_stride;
+  a.src = nullptr;
+  a.src_stride = 0;
+  a.mass4 = o.m_q + 4.0;
+  a.nrhs = o.nrhs;
+  a.remap = 1;
+  a.sub_alpha = 0;
+  a.gate = kGateNone;
+  return a;
+}
+
+// ------------------------------------------------- launch config cache ---
+namespace {
+std::mutex g_cfg_mu;
+std::map<std::string, LaunchCfg> g_cfg;
+bool g_cfg_loaded = false;
+
+std::string device_name() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string s = p.gcnArchName;
+  for (char& ch : s)
+    if (ch == ' ' || ch == '|') ch = '_';
+  return s;
+}
+
+std::string cfg_key(const OpInfo& o) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s|%dx%dx%dx%d|p%d|l%d|n%d", device_name().c_str(), o.g.X, o.g.Y, o.g.Z,
+           o.g.T, o.prec, o.link, o.nrhs);
+  return buf;
+}
+
+void load_cache_file_locked() {
+  if (g_cfg_loaded) return;
+  g_cfg_loaded = true;
+  const char* path = std::getenv("DIRAC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  LaunchCfg c;
+  while (std::fscanf(f, "%255s %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds) == 5) {
+    c.tuned = 1;
+    g_cfg[key] = c;
+  }
+  std::fclose(f);
+}
+
+LaunchCfg default_cfg(const OpInfo& o) {
+  LaunchCfg c;
+  c.S = 256;
+  c.remap = 1;
+  c.lds = 0;
+  c.tuned = 0;
+  if (o.nrhs == 1)
+    c.R = 1;
+  else
+    c.R = std::min(o.nrhs, o.prec == DIRAC_F64 ? 2 : 3);
+  return c;
+}
+}  // namespace
+
+LaunchCfg launch_cfg(const OpInfo& o) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  load_cache_file_locked();
+  auto it = g_cfg.find(cfg_key(o));
+  if (it != g_cfg.end()) return it->second;
+  return default_cfg(o);
+}
+
+static void store_cfg(const OpInfo& o, const LaunchCfg& c, bool to_file) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  load_cache_file_locked();
+  const std::string key = cfg_key(o);
+  g_cfg[key] = c;
+  if (!to_file) return;
+  const char* path = std::getenv("DIRAC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c.S, c.R, c.remap, c.lds);
+  std::fclose(f);
+}
+
+// ---------------------------------------------------------- scratch -----
+namespace {
+struct DevScratch {
+  double* partials = nullptr;
+  int64_t partial_cap = 0;
+  unsigned* counter = nullptr;
+  CgState* state = nullptr;
+};
+std::mutex g_scratch_mu;
+std::map<int, DevScratch> g_scratch;
+}  // namespace
+
+int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(DIRAC_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  DevScratch& s = g_scratch[dev];
+  if (s.counter == nullptr) {
+    if (hipMalloc(&s.counter, 256) != hipSuccess) return set_error(DIRAC_EDEVICE, "scratch allocation failed");
+    if (hipMemset(s.counter, 0, 256) != hipSuccess) return set_error(DIRAC_EDEVICE, "scratch clear failed");
+    if (hipMalloc(&s.state, sizeof(CgState) * kMaxRhs) != hipSuccess)
+      return set_error(DIRAC_EDEVICE, "scratch allocation failed");
+    if (hipMemset(s.state, 0, sizeof(CgState) * kMaxRhs) != hipSuccess)
+      return set_error(DIRAC_EDEVICE, "scratch clear failed");
+  }
+  if (s.partial_cap < partial_doubles) {
+    if (s.partials) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(s.partials);
+      s.partials = nullptr;
+    }
+    int64_t cap = std::max<int64_t>(partial_doubles, 1 << 16);
+    if (hipMalloc(&s.partials, cap * sizeof(double)) != hipSuccess) {
+      s.partial_cap = 0;
+      return set_error(DIRAC_EDEVICE, "scratch allocation failed");
+    }
+    s.partial_cap = cap;
+  }
+  (void)nrhs;
+  out->partials = s.partials;
+  out->counter = s.counter;
+  out->state = s.state;
+  return DIRAC_OK;
+}
+
+// Serialises API calls that use the library scratch.
+static std::mutex g_api_mu;
+
+}  // namespace dirac
+
+using namespace dirac;
+
+// ----------------------------------------------------------- helpers -----
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static bool overlap(const void* a, int64_t na, const void* b, int64_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+static int check_ptr(const void* p, const char* name, const char* what) {
+  if (p == nullptr) return set_error(DIRAC_EINVAL, "%s: %s is NULL", what, name);
+  if (!aligned16(p)) return set_error(DIRAC_EINVAL, "%s: %s is not 16-byte aligned", what, name);
+  return DIRAC_OK;
+}
+
+static int64_t spinor_buffer_bytes(const OpInfo& o) {
+  return (o.nrhs - 1) * o.field_stride + o.field_bytes;
+}
+
+#define CHECK(x)              \
+  do {                        \
+    int rc_ = (x);            \
+    if (rc_ != DIRAC_OK) return rc_; \
+  } while (0)
+
+extern "C" {
+
+const char* dirac_last_error(void) { return g_error.c_str(); }
+
+const char* dirac_version(void) { return "dirac 0.1 gfx950"; }
+
+int64_t dirac_spinor_bytes(const dirac_op* op) {
+  OpInfo o;
+  int rc = check_op(op, &o, "dirac_spinor_bytes");
+  if (rc != DIRAC_OK) return rc;
+  return o.nrhs * o.field_stride;
+}
+
+int64_t dirac_gauge_bytes(const dirac_op* op) {
+  OpInfo o;
+  int rc = check_op(op, &o, "dirac_gauge_bytes");
+  if (rc != DIRAC_OK) return rc;
+  return o.gauge_bytes;
+}
+
+int dirac_pack_gauge(const dirac_op* op, const void* U_c128, void* U_int, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_pack_gauge"));
+  CHECK(check_ptr(U_c128, "U_c128", "dirac_pack_gauge"));
+  CHECK(check_ptr(U_int, "U_int", "dirac_pack_gauge"));
+  if (overlap(U_c128, o.V * 576, U_int, o.gauge_bytes))
+    return set_error(DIRAC_EINVAL, "dirac_pack_gauge: input and output overlap");
+  return hip_status(pack_gauge(o.g, o.prec, o.link, U_c128, U_int, (hipStream_t)stream), "pack_gauge");
+}
+
+int dirac_pack_spinor(const dirac_op* op, const void* psi_c128, void* psi_int, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_pack_spinor"));
+  CHECK(check_ptr(psi_c128, "psi_c128", "dirac_pack_spinor"));
+  CHECK(check_ptr(psi_int, "psi_int", "dirac_pack_spinor"));
+  if (overlap(psi_c128, o.nrhs * o.V * 192, psi_int, spinor_buffer_bytes(o)))
+    return set_error(DIRAC_EINVAL, "dirac_pack_spinor: input and output overlap");
+  return hip_status(pack_spinor(o.g, o.nrhs, psi_c128, field_of(o, psi_int), (hipStream_t)stream),
+                    "pack_spinor");
+}
+
+int dirac_unpack_spinor(const dirac_op* op, const void* psi_int, void* psi_c128, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_unpack_spinor"));
+  CHECK(check_ptr(psi_c128, "psi_c128", "dirac_unpack_spinor"));
+  CHECK(check_ptr(psi_int, "psi_int", "dirac_unpack_spinor"));
+  if (overlap(psi_c128, o.nrhs * o.V * 192, psi_int, spinor_buffer_bytes(o)))
+    return set_error(DIRAC_EINVAL, "dirac_unpack_spinor: input and output overlap");
+  return hip_status(unpack_spinor(o.g, o.nrhs, field_of(o, psi_int), psi_c128, (hipStream_t)stream),
+                    "unpack_spinor");
+}
+
+int dirac_convert_spinor(const dirac_op* op_src, const void* src, const dirac_op* op_dst, void* dst,
+                         void* stream) {
+  clear_error();
+  OpInfo a, b;
+  CHECK(check_op(op_src, &a, "dirac_convert_spinor"));
+  CHECK(check_op(op_dst, &b, "dirac_convert_spinor"));
+  for (int d = 0; d < 4; ++d)
+    if (op_src->L[d] != op_dst->L[d]) return set_error(DIRAC_EINVAL, "dirac_convert_spinor: geometries differ");
+  if (a.nrhs != b.nrhs) return set_error(DIRAC_EINVAL, "dirac_convert_spinor: nrhs differ");
+  CHECK(check_ptr(src, "src", "dirac_convert_spinor"));
+  CHECK(check_ptr(dst, "dst", "dirac_convert_spinor"));
+  if (overlap(src, spinor_buffer_bytes(a), dst, spinor_buffer_bytes(b)))
+    return set_error(DIRAC_EINVAL, "dirac_convert_spinor: input and output overlap");
+  return hip_status(convert_scale(a.g, a.nrhs, field_of(a, src), field_of(b, dst), nullptr, -1, nullptr,
+                                  (hipStream_t)stream),
+                    "convert");
+}
+
+static int apply_common(const dirac_op* op, const void* U, const void* psi, void* chi, void* stream, int dag,
+                        const char* what) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, what));
+  CHECK(check_ptr(U, "U_int", what));
+  CHECK(check_ptr(psi, "psi_int", what));
+  CHECK(check_ptr(chi, "chi_int", what));
+  const int64_t sb = spinor_buffer_bytes(o);
+  if (overlap(psi, sb, chi, sb) || overlap(U, o.gauge_bytes, chi, sb))
+    return set_error(DIRAC_EINVAL, "%s: output overlaps an input", what);
+  DslashArgs a = dslash_args(o, U, psi, chi);
+  return run_dslash(o.prec, o.prec, o.link, dag, kEpiStore, launch_cfg(o), a, (hipStream_t)stream);
+}
+
+int dirac_apply(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int, void* stream) {
+  return apply_common(op, U_int, psi_int, chi_int, stream, 0, "dirac_apply");
+}
+
+int dirac_dagger_apply(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int,
+                       void* stream) {
+  return apply_common(op, U_int, psi_int, chi_int, stream, 1, "dirac_dagger_apply");
+}
+
+int dirac_mdagm_apply(const dirac_op* op, const void* U_int, const void* psi_int, void* tmp_int, void* chi_int,
+                      void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_mdagm_apply"));
+  CHECK(check_ptr(tmp_int, "tmp_int", "dirac_mdagm_apply"));
+  const int64_t sb = spinor_buffer_bytes(o);
+  if (overlap(tmp_int, sb, psi_int, sb) || overlap(tmp_int, sb, chi_int, sb))
+    return set_error(DIRAC_EINVAL, "dirac_mdagm_apply: tmp overlaps another buffer");
+  CHECK(apply_common(op, U_int, psi_int, tmp_int, stream, 0, "dirac_mdagm_apply"));
+  return apply_common(op, U_int, tmp_int, chi_int, stream, 1, "dirac_mdagm_apply");
+}
+
+int dirac_field_dot(const dirac_op* op, const void* a, const void* b, double* out_host, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_field_dot"));
+  CHECK(check_ptr(a, "a_int", "dirac_field_dot"));
+  CHECK(check_ptr(b, "b_int", "dirac_field_dot"));
+  if (out_host == nullptr) return set_error(DIRAC_EINVAL, "dirac_field_dot: out_host is NULL");
+  std::lock_guard<std::mutex> lk(g_api_mu);
+  Scratch s;
+  const int64_t nparts = 2 * ((o.g.Vh + 255) / 256);
+  CHECK(lib_scratch(nparts * o.nrhs * 2, o.nrhs, &s));
+  hipStream_t st = (hipStream_t)stream;
+  RedTarget red{s.partials, s.counter, s.state, kFinPlain};
+  CHECK(hip_status(dot(o.g, o.nrhs, field_of(o, a), field_of(o, b), red, st), "dot"));
+  std::vector<CgState> hs(o.nrhs);
+  CHECK(hip_status(hipMemcpyAsync(hs.data(), s.state, sizeof(CgState) * o.nrhs, hipMemcpyDeviceToHost, st),
+                   "dot readback"));
+  CHECK(hip_status(hipStreamSynchronize(st), "dot sync"));
+  for (int r = 0; r < o.nrhs; ++r) {
+    out_host[2 * r] = hs[r].res[0];
+    out_host[2 * r + 1] = hs[r].res[1];
+  }
+  return DIRAC_OK;
+}
+
+int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x, void* y, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_field_axpy"));
+  CHECK(check_ptr(x, "x_int", "dirac_field_axpy"));
+  CHECK(check_ptr(y, "y_int", "dirac_field_axpy"));
+  if (!std::isfinite(a_re) || !std::isfinite(a_im))
+    return set_error(DIRAC_EINVAL, "dirac_field_axpy: a must be finite");
+  const int64_t sb = spinor_buffer_bytes(o);
+  if (overlap(x, sb, y, sb)) return set_error(DIRAC_EINVAL, "dirac_field_axpy: x and y overlap");
+  return hip_status(axpby(o.g, o.nrhs, field_of(o, x), field_of(o, y), nullptr, a_re, a_im, 1.0, 0.0,
+                          (hipStream_t)stream),
+                    "axpy");
+}
+
+int dirac_force(const dirac_op* op, const void* g_int, const void* psi_int, void* F_c128, double coeff,
+                int32_t accumulate, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_force"));
+  if (o.prec != DIRAC_F64 && o.prec != DIRAC_F32)
+    return set_error(DIRAC_EUNSUPPORTED, "dirac_force: F64 or F32 spinors only");
+  if (o.nrhs != 1) return set_error(DIRAC_EINVAL, "dirac_force: nrhs must be 1");
+  CHECK(check_ptr(g_int, "g_int", "dirac_force"));
+  CHECK(check_ptr(psi_int, "psi_int", "dirac_force"));
+  CHECK(check_ptr(F_c128, "F_c128", "dirac_force"));
+  if (!std::isfinite(coeff)) return set_error(DIRAC_EINVAL, "dirac_force: coeff must be finite");
+  const int64_t fb = o.V * 4 * 9 * 16;
+  if (overlap(F_c128, fb, g_int, o.field_bytes) || overlap(F_c128, fb, psi_int, o.field_bytes))
+    return set_error(DIRAC_EINVAL, "dirac_force: output overlaps an input");
+  return hip_status(force(o.g, o.prec, g_int, psi_int, o.field_bytes, F_c128, coeff, accumulate ? 1 : 0,
+                          (hipStream_t)stream),
+                    "force");
+}
+
+int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U, const void* const* psi,
+                      void* const* chi, int32_t dagger, void* stream) {
+  clear_error();
+  if (n < 1 || n > 8) return set_error(DIRAC_EINVAL, "dirac_multi_apply: n must be in 1..8");
+  if (!ops || !U || !psi || !chi) return set_error(DIRAC_EINVAL, "dirac_multi_apply: NULL array");
+  std::vector<OpInfo> infos(n);
+  for (int k = 0; k < n; ++k) {
+    CHECK(check_op(&ops[k], &infos[k], "dirac_multi_apply"));
+    if (infos[k].nrhs != 1) return set_error(DIRAC_EINVAL, "dirac_multi_apply: nrhs must be 1");
+    if (infos[k].prec != infos[0].prec || infos[k].link != infos[0].link)
+      return set_error(DIRAC_EINVAL, "dirac_multi_apply: all lattices share one precision and link format");
+    CHECK(check_ptr(U[k], "U", "dirac_multi_apply"));
+    CHECK(check_ptr(psi[k], "psi", "dirac_multi_apply"));
+    CHECK(check_ptr(chi[k], "chi", "dirac_multi_apply"));
+    if (overlap(psi[k], infos[k].field_bytes, chi[k], infos[k].field_bytes))
+      return set_error(DIRAC_EINVAL, "dirac_multi_apply: output overlaps input");
+  }
+  return multi_apply(n, infos.data(), U, psi, chi, dagger ? 1 : 0, (hipStream_t)stream);
+}
+
+// --------------------------------------------------------- graph plans ----
+struct dirac_plan_t {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+int dirac_multi_plan_create(int32_t n, const dirac_op* ops, const void* const* U, const void* const* psi,
+                            void* const* chi, int32_t dagger, void* stream, void** plan_out) {
+  clear_error();
+  if (plan_out == nullptr) return set_error(DIRAC_EINVAL, "dirac_multi_plan_create: plan_out is NULL");
+  *plan_out = nullptr;
+  hipStream_t cap;
+  CHECK(hip_status(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "plan stream"));
+  int rc = hip_status(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (rc == DIRAC_OK) {
+    rc = dirac_multi_apply(n, ops, U, psi, chi, dagger, cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (rc == DIRAC_OK) rc = hip_status(e, "end capture");
+    if (rc == DIRAC_OK) {
+      hipGraphExec_t exec = nullptr;
+      rc = hip_status(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+      if (rc == DIRAC_OK) {
+        dirac_plan_t* p = new dirac_plan_t{graph, exec};
+        *plan_out = p;
+      } else {
+        (void)hipGraphDestroy(graph);
+      }
+    } else if (graph) {
+      (void)hipGraphDestroy(graph);
+    }
+  }
+  (void)hipStreamDestroy(cap);
+  (void)stream;
+  return rc;
+}
+
+int dirac_plan_launch(void* plan, void* stream) {
+  clear_error();
+  if (plan == nullptr) return set_error(DIRAC_EINVAL, "dirac_plan_launch: plan is NULL");
+  dirac_plan_t* p = (dirac_plan_t*)plan;
+  return hip_status(hipGraphLaunch(p->exec, (hipStream_t)stream), "graph launch");
+}
+
+int dirac_plan_destroy(void* plan) {
+  clear_error();
+  if (plan == nullptr) return DIRAC_OK;
+  dirac_plan_t* p = (dirac_plan_t*)plan;
+  (void)hipGraphExecDestroy(p->exec);
+  (void)hipGraphDestroy(p->graph);
+  delete p;
+  return DIRAC_OK;
+}
+
+// ------------------------------------------------------------ tuning -----
+int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int, void* stream) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_autotune"));
+  CHECK(check_ptr(U_int, "U_int", "dirac_autotune"));
+  CHECK(check_ptr(psi_int, "psi_int", "dirac_autotune"));
+  CHECK(check_ptr(chi_int, "chi_int", "dirac_autotune"));
+  const int64_t sb = spinor_buffer_bytes(o);
+  if (overlap(psi_int, sb, chi_int, sb)) return set_error(DIRAC_EINVAL, "dirac_autotune: psi and chi overlap");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  CHECK(hip_status(hipEventCreate(&e0), "event"));
+  CHECK(hip_status(hipEventCreate(&e1), "event"));
+  DslashArgs a = dslash_args(o, U_int, psi_int, chi_int);
+  // Enough launches to be well above the timer resolution.
+  const double est_us = std::max(5.0, o.V * 1e-4);
+  const int reps = (int)std::min(200.0, std::max(5.0, 2000.0 / est_us));
+  LaunchCfg best{};
+  float best_ms = 1e30f;
+  int rc = DIRAC_OK;
+  for (int S : {64, 128, 256}) {
+    for (int remap : {0, 1}) {
+      for (int R = 1; R <= std::min(4, o.nrhs); ++R) {
+        if (o.nrhs > 1 && R == 1 && o.nrhs > 4) continue;
+        LaunchCfg c{S, R, remap, 0, 1};
+        rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
+        if (rc != DIRAC_OK) break;
+        rc = hip_status(hipEventRecord(e0, st), "event record");
+        for (int k = 0; k < reps && rc == DIRAC_OK; ++k) rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
+        if (rc == DIRAC_OK) rc = hip_status(hipEventRecord(e1, st), "event record");
+        if (rc == DIRAC_OK) rc = hip_status(hipEventSynchronize(e1), "event sync");
+        if (rc != DIRAC_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      if (rc != DIRAC_OK) break;
+    }
+    if (rc != DIRAC_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != DIRAC_OK) return rc;
+  store_cfg(o, best, true);
+  return DIRAC_OK;
+}
+
+int dirac_launch_config(const dirac_op* op, int32_t* block_sites, int32_t* rhs_per_thread, int32_t* xcd_remap,
+                        int32_t* lds, int32_t* tuned) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_launch_config"));
+  LaunchCfg c = launch_cfg(o);
+  if (block_sites) *block_sites = c.S;
+  if (rhs_per_thread) *rhs_per_thread = c.R;
+  if (xcd_remap) *xcd_remap = c.remap;
+  if (lds) *lds = c.lds;
+  if (tuned) *tuned = c.tuned;
+  return DIRAC_OK;
+}
+
+int dirac_set_launch_config(const dirac_op* op, int32_t block_sites, int32_t rhs_per_thread, int32_t xcd_remap,
+                            int32_t lds) {
+  clear_error();
+  OpInfo o;
+  CHECK(check_op(op, &o, "dirac_set_launch_config"));
+  if (block_sites != 64 && block_sites != 128 && block_sites != 256)
+    return set_error(DIRAC_EINVAL, "dirac_set_launch_config: block_sites must be 64, 128 or 256");
+  if (rhs_per_thread < 1 || rhs_per_thread > 4)
+    return set_error(DIRAC_EINVAL, "dirac_set_launch_config: rhs_per_thread must be 1..4");
+  if (lds != 0) return set_error(DIRAC_EUNSUPPORTED, "dirac_set_launch_config: lds staging is not built");
+  LaunchCfg c{block_sites, rhs_per_thread, xcd_remap ? 1 : 0, 0, 1};
+  store_cfg(o, c, false);
+  return DIRAC_OK;
+}
+
+}  // extern "C"

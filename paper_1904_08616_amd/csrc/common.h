@@ -1,0 +1,647 @@
+// Shared device-side building blocks of libdirac: lattice geometry and the
+// even-odd site map, complex arithmetic, the internal storage formats of
+// spinors and links, SU(3) row reconstruction, the per-direction spin
+// projections of eq. (1), and a deterministic float64 grid reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "dirac.h"
+
+namespace dirac {
+
+constexpr int kNumXcd = 8;       // MI355X: 8 XCDs, 32 CUs each
+constexpr int kMaxRhs = 12;
+
+// --------------------------------------------------------------- geometry --
+// Sites are split by parity p = (x+y+z+t) & 1; within a parity the
+// checkerboard index is i = n >> 1 where n = ((t*Z + z)*Y + y)*X + x is the
+// lexicographic site number (x fastest).  X even makes this a bijection.
+struct Geom {
+  int X, Y, Z, T;
+  int Xh;  // X / 2
+  int Vh;  // sites per parity
+  int sZ;  // checkerboard stride of z: Xh * Y
+  int sT;  // checkerboard stride of t: Xh * Y * Z
+};
+
+inline Geom make_geom(const int L[4]) {
+  Geom g;
+  g.X = L[0]; g.Y = L[1]; g.Z = L[2]; g.T = L[3];
+  g.Xh = g.X / 2;
+  g.sZ = g.Xh * g.Y;
+  g.sT = g.sZ * g.Z;
+  g.Vh = g.sT * g.T;
+  return g;
+}
+
+struct Coord { int x, y, z, t; };
+
+__device__ __forceinline__ Coord cb_coords(const Geom& g, int p, int i) {
+  Coord c;
+  int xh = i % g.Xh;
+  int r = i / g.Xh;
+  c.y = r % g.Y;
+  r /= g.Y;
+  c.z = r % g.Z;
+  c.t = r / g.Z;
+  c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
+  return c;
+}
+
+// Checkerboard index (in the opposite parity) of the forward / backward
+// neighbour of site (c, i) in direction MU.
+template <int MU>
+__device__ __forceinline__ int nb_fwd(const Geom& g, const Coord& c, int i) {
+  if constexpr (MU == 0) {
+    int xn = (c.x + 1 == g.X) ? 0 : c.x + 1;
+    return i - (c.x >> 1) + (xn >> 1);
+  } else if constexpr (MU == 1) {
+    return (c.y + 1 == g.Y) ? i - (g.Y - 1) * g.Xh : i + g.Xh;
+  } else if constexpr (MU == 2) {
+    return (c.z + 1 == g.Z) ? i - (g.Z - 1) * g.sZ : i + g.sZ;
+  } else {
+    return (c.t + 1 == g.T) ? i - (g.T - 1) * g.sT : i + g.sT;
+  }
+}
+
+template <int MU>
+__device__ __forceinline__ int nb_bwd(const Geom& g, const Coord& c, int i) {
+  if constexpr (MU == 0) {
+    int xn = (c.x == 0) ? g.X - 1 : c.x - 1;
+    return i - (c.x >> 1) + (xn >> 1);
+  } else if constexpr (MU == 1) {
+    return (c.y == 0) ? i + (g.Y - 1) * g.Xh : i - g.Xh;
+  } else if constexpr (MU == 2) {
+    return (c.z == 0) ? i + (g.Z - 1) * g.sZ : i - g.sZ;
+  } else {
+    return (c.t == 0) ? i + (g.T - 1) * g.sT : i - g.sT;
+  }
+}
+
+// Block index -> logical tile index so that each XCD (blocks are handed to
+// the 8 XCDs round-robin) walks one contiguous range of tiles: neighbouring
+// tiles then share that XCD's L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks, int remap) {
+  if (!remap) return b;
+  int q = nblocks / kNumXcd, rem = nblocks % kNumXcd;
+  int xcd = b % kNumXcd, slot = b / kNumXcd;
+  return (xcd < rem) ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
+// ---------------------------------------------------------------- complex --
+template <class R> struct Cx { R re, im; };
+
+template <class R> __device__ __forceinline__ Cx<R> cx(R a, R b) { return Cx<R>{a, b}; }
+template <class R> __device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> __device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+template <class R> __device__ __forceinline__ Cx<R> mul_i(Cx<R> a) { return {-a.im, a.re}; }    // i a
+template <class R> __device__ __forceinline__ Cx<R> mul_mi(Cx<R> a) { return {a.im, -a.re}; }   // -i a
+template <class R> __device__ __forceinline__ Cx<R> neg(Cx<R> a) { return {-a.re, -a.im}; }
+template <class R> __device__ __forceinline__ Cx<R> conj(Cx<R> a) { return {a.re, -a.im}; }
+// a * b
+template <class R> __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <class R> __device__ __forceinline__ Cx<R> cmadd(Cx<R> acc, Cx<R> a, Cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + conj(a) * b
+template <class R> __device__ __forceinline__ Cx<R> cjmadd(Cx<R> acc, Cx<R> a, Cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
+
+template <class R> struct M3 { Cx<R> e[3][3]; };
+
+// Row 2 of an SU(3) matrix from rows 0 and 1: conj(row0 x row1).
+template <class R> __device__ __forceinline__ void su3_row2(M3<R>& u) {
+  auto cr = [](Cx<R> a, Cx<R> b, Cx<R> c, Cx<R> d) {  // conj(a*b - c*d)
+    Cx<R> v = cmul(a, b) - cmul(c, d);
+    return conj(v);
+  };
+  u.e[2][0] = cr(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1]);
+  u.e[2][1] = cr(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2]);
+  u.e[2][2] = cr(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
+}
+
+// ------------------------------------------------------- storage formats --
+// Spinor fields: per right-hand side, [parity][NV][Vh] 16-byte vectors,
+// followed for scaled formats by a float scale per site [parity][Vh].
+// Component c = 3*spin + colour.
+//   F64  : NV = 12, double2 = one complex each
+//   F32  : NV = 6,  float4  = two complex each
+//   F16S : NV = 3,  8 x half = four complex each, times the site scale
+//   BF16S: NV = 3,  8 x bfloat16, times the site scale
+template <int P> struct SpinFmt;
+
+__device__ __forceinline__ float bf16_to_f(unsigned short b) {
+  return __uint_as_float(((unsigned)b) << 16);
+}
+// float -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ unsigned short f_to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float h_to_f(unsigned short h) {
+  return __half2float(__ushort_as_half(h));
+}
+__device__ __forceinline__ unsigned short f_to_h(float f) {
+  return __half_as_ushort(__float2half_rn(f));
+}
+
+// Fields are read and written with raw buffer instructions: a 128-bit
+// resource (base, size) in scalar registers, a wave-uniform component-plane
+// offset in a scalar register and one 32-bit per-lane offset shared by all
+// planes.  This keeps address arithmetic out of the vector register budget,
+// and the hardware range check turns any access past the field's end into a
+// zero load / dropped store instead of a memory fault.  One field (one
+// right-hand side) must therefore be smaller than 4 GiB.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T bld(Rsrc r, uint32_t voff, uint32_t soff) {
+  static_assert(sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4, "buffer load size");
+  if constexpr (sizeof(T) == 16) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  } else if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+}
+template <class T>
+__device__ __forceinline__ void bst(Rsrc r, uint32_t voff, uint32_t soff, const T& v) {
+  static_assert(sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4, "buffer store size");
+  if constexpr (sizeof(T) == 16) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+  } else if constexpr (sizeof(T) == 8) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  }
+}
+
+template <> struct SpinFmt<DIRAC_F64> {
+  using R = double;
+  static constexpr int NV = 12;
+  static constexpr bool kScaled = false;
+  static constexpr int kSiteBytes = 192;
+  __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      double2 t = bld<double2>(f, o, base + (uint32_t)c * (uint32_t)Vh * 16u);
+      v[c] = {t.x, t.y};
+    }
+  }
+  __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
+  __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+      bst(f, o, base + (uint32_t)c * (uint32_t)Vh * 16u, make_double2(v[c].re, v[c].im));
+  }
+};
+
+template <> struct SpinFmt<DIRAC_F32> {
+  using R = float;
+  static constexpr int NV = 6;
+  static constexpr bool kScaled = false;
+  static constexpr int kSiteBytes = 96;
+  __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float4 t = bld<float4>(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
+      v[2 * k] = {t.x, t.y};
+      v[2 * k + 1] = {t.z, t.w};
+    }
+  }
+  __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
+  __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      bst(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u,
+          make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
+  }
+};
+
+template <bool BF> struct SpinScaled {
+  using R = float;
+  static constexpr int NV = 3;
+  static constexpr bool kScaled = true;
+  static constexpr int kSiteBytes = 52;
+  __device__ static __forceinline__ float dec(unsigned short h) { return BF ? bf16_to_f(h) : h_to_f(h); }
+  __device__ static __forceinline__ unsigned short enc(float f) { return BF ? f_to_bf16(f) : f_to_h(f); }
+  // the scales follow the 2 * Vh * 48 payload bytes
+  __device__ static __forceinline__ uint32_t scale_off(int Vh, int p) {
+    return (uint32_t)Vh * 96u + (uint32_t)p * (uint32_t)Vh * 4u;
+  }
+  __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
+    const float s = bld<float>(f, (uint32_t)i * 4u, scale_off(Vh, p));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 t = bld<uint4>(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
+      unsigned w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[4 * k + j] = {s * dec((unsigned short)(w[j] & 0xFFFFu)), s * dec((unsigned short)(w[j] >> 16))};
+    }
+  }
+  // Replace v by the value the store would leave in memory.
+  __device__ static __forceinline__ void round(Cx<R> (&v)[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      v[c].re = (m > 0.f) ? m * dec(enc(v[c].re / m)) : 0.f;
+      v[c].im = (m > 0.f) ? m * dec(enc(v[c].im / m)) : 0.f;
+    }
+  }
+  __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      unsigned w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        // divide (not multiply by 1/m) so the site maximum maps to +-1 exactly
+        float re = (m > 0.f) ? v[4 * k + j].re / m : 0.f;
+        float im = (m > 0.f) ? v[4 * k + j].im / m : 0.f;
+        w[j] = (unsigned)enc(re) | ((unsigned)enc(im) << 16);
+      }
+      bst(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));
+    }
+    bst(f, (uint32_t)i * 4u, scale_off(Vh, p), m);
+  }
+};
+template <> struct SpinFmt<DIRAC_F16S> : SpinScaled<false> {};
+template <> struct SpinFmt<DIRAC_BF16S> : SpinScaled<true> {};
+
+// Bytes of one spinor field (one right-hand side) in format P.
+__host__ __device__ inline int64_t spinor_field_bytes(int prec, int64_t V) {
+  switch (prec) {
+    case DIRAC_F64: return V * 192;
+    case DIRAC_F32: return V * 96;
+    default: return V * 48 + V * 4;
+  }
+}
+
+// Gauge links: [parity][mu][NL][Vh] vectors.  Entry k = 3*row + col of the
+// row-major colour matrix; LINK12 stores rows 0 and 1 only.
+//   F64 18: 9 double2     F64 12: 6 double2
+//   F32 18: 9 float2      F32 12: 3 float4 (two entries each)
+//   F16S/BF16S 12: 3 x (4 x 16-bit) = two entries each, unscaled
+template <int P, int LK> struct LinkFmt;
+
+template <int LK> struct LinkF64 {
+  using R = double;
+  static constexpr int NL = LK / 2;
+  static constexpr int kBytes = LK * 8;
+  __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)((p * 4 + mu) * NL) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      double2 t = bld<double2>(U, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
+      u.e[k / 3][k % 3] = {t.x, t.y};
+    }
+    if constexpr (LK == 12) su3_row2(u);
+  }
+};
+template <> struct LinkFmt<DIRAC_F64, 18> : LinkF64<18> {};
+template <> struct LinkFmt<DIRAC_F64, 12> : LinkF64<12> {};
+
+template <> struct LinkFmt<DIRAC_F32, 18> {
+  using R = float;
+  static constexpr int NL = 9;
+  static constexpr int kBytes = 72;
+  __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
+    const uint32_t o = (uint32_t)i * 8u;
+    const uint32_t base = (uint32_t)((p * 4 + mu) * 9) * (uint32_t)Vh * 8u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float2 t = bld<float2>(U, o, base + (uint32_t)k * (uint32_t)Vh * 8u);
+      u.e[k / 3][k % 3] = {t.x, t.y};
+    }
+  }
+};
+template <> struct LinkFmt<DIRAC_F32, 12> {
+  using R = float;
+  static constexpr int NL = 3;
+  static constexpr int kBytes = 48;
+  __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
+    const uint32_t o = (uint32_t)i * 16u;
+    const uint32_t base = (uint32_t)((p * 4 + mu) * 3) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float4 t = bld<float4>(U, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
+      u.e[(2 * k) / 3][(2 * k) % 3] = {t.x, t.y};
+      u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {t.z, t.w};
+    }
+    su3_row2(u);
+  }
+};
+template <bool BF> struct LinkHalf12 {
+  using R = float;
+  static constexpr int NL = 3;
+  static constexpr int kBytes = 24;
+  __device__ static __forceinline__ float dec(unsigned short h) { return BF ? bf16_to_f(h) : h_to_f(h); }
+  __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
+    const uint32_t o = (uint32_t)i * 8u;
+    const uint32_t base = (uint32_t)((p * 4 + mu) * 3) * (uint32_t)Vh * 8u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint2 t = bld<uint2>(U, o, base + (uint32_t)k * (uint32_t)Vh * 8u);
+      u.e[(2 * k) / 3][(2 * k) % 3] = {dec(t.x & 0xFFFFu), dec(t.x >> 16)};
+      u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {dec(t.y & 0xFFFFu), dec(t.y >> 16)};
+    }
+    su3_row2(u);
+  }
+};
+template <> struct LinkFmt<DIRAC_F16S, 12> : LinkHalf12<false> {};
+template <> struct LinkFmt<DIRAC_BF16S, 12> : LinkHalf12<true> {};
+
+__host__ __device__ inline int64_t link_bytes(int prec, int link) {
+  if (prec == DIRAC_F64) return link * 8;
+  if (prec == DIRAC_F32) return link * 4;
+  return link * 2;
+}
+
+// -------------------------------------------------- spin projection ------
+// Chiral basis: gamma_mu = [[0, s_mu], [s_mu^dag, 0]] with s_1 = -i sigma_x,
+// s_2 = -i sigma_y, s_3 = -i sigma_z, s_4 = 1.  For psi = (u, d) (upper and
+// lower spin pairs) and sign s = +-1:
+//   (1 - s gamma) psi = (h, -s s_mu^dag h),  h = u - s s_mu d
+//   (1 + s gamma) psi = (h,  s s_mu^dag h),  h = u + s s_mu d
+// so each hop needs one half spinor (two colour vectors) and one SU(3)
+// product per spin row of the half spinor.
+
+// (s_mu d)_k for spin k = 0, 1 of the half spinor; d0/d1 colour component a.
+template <int MU, int K, class R>
+__device__ __forceinline__ Cx<R> sig_d(Cx<R> d0, Cx<R> d1) {
+  if constexpr (MU == 0) return K == 0 ? mul_mi(d1) : mul_mi(d0);  // (-i d1, -i d0)
+  else if constexpr (MU == 1) return K == 0 ? neg(d1) : d0;        // (-d1, d0)
+  else if constexpr (MU == 2) return K == 0 ? mul_mi(d0) : mul_i(d1);  // (-i d0, i d1)
+  else return K == 0 ? d0 : d1;                                    // (d0, d1)
+}
+
+// (s_mu^dag h)_k for spin k = 0, 1 of the lower pair.
+template <int MU, int K, class R>
+__device__ __forceinline__ Cx<R> sigdag_h(Cx<R> h0, Cx<R> h1) {
+  if constexpr (MU == 0) return K == 0 ? mul_i(h1) : mul_i(h0);    // (i h1, i h0)
+  else if constexpr (MU == 1) return K == 0 ? h1 : neg(h0);        // (h1, -h0)
+  else if constexpr (MU == 2) return K == 0 ? mul_i(h0) : mul_mi(h1);  // (i h0, -i h1)
+  else return K == 0 ? h0 : h1;                                    // (h0, h1)
+}
+
+// Half spinor h = u + SG * s_mu d of a full spinor v (SG = +1 or -1).
+template <int MU, int SG, class R>
+__device__ __forceinline__ void project(const Cx<R> (&v)[12], Cx<R> (&h)[2][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Cx<R> d0 = v[6 + a], d1 = v[9 + a];
+    Cx<R> e0 = sig_d<MU, 0>(d0, d1), e1 = sig_d<MU, 1>(d0, d1);
+    if constexpr (SG > 0) {
+      h[0][a] = v[a] + e0;
+      h[1][a] = v[3 + a] + e1;
+    } else {
+      h[0][a] = v[a] - e0;
+      h[1][a] = v[3 + a] - e1;
+    }
+  }
+}
+
+// acc += (w, SG * s_mu^dag w) for a half spinor w (the hop's contribution).
+template <int MU, int SG, class R>
+__device__ __forceinline__ void reconstruct_add(Cx<R> (&acc)[12], const Cx<R> (&w)[2][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a] = acc[a] + w[0][a];
+    acc[3 + a] = acc[3 + a] + w[1][a];
+    Cx<R> l0 = sigdag_h<MU, 0>(w[0][a], w[1][a]);
+    Cx<R> l1 = sigdag_h<MU, 1>(w[0][a], w[1][a]);
+    if constexpr (SG > 0) {
+      acc[6 + a] = acc[6 + a] + l0;
+      acc[9 + a] = acc[9 + a] + l1;
+    } else {
+      acc[6 + a] = acc[6 + a] - l0;
+      acc[9 + a] = acc[9 + a] - l1;
+    }
+  }
+}
+
+// w = U h, and w = U^dag h, per spin row of the half spinor.
+template <class R>
+__device__ __forceinline__ void su3_mul(const M3<R>& u, const Cx<R> (&h)[2][3], Cx<R> (&w)[2][3]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> t = cmul(u.e[a][0], h[s][0]);
+      t = cmadd(t, u.e[a][1], h[s][1]);
+      t = cmadd(t, u.e[a][2], h[s][2]);
+      w[s][a] = t;
+    }
+}
+template <class R>
+__device__ __forceinline__ void su3_dag_mul(const M3<R>& u, const Cx<R> (&h)[2][3], Cx<R> (&w)[2][3]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> t = cmul(conj(u.e[0][a]), h[s][0]);
+      t = cjmadd(t, u.e[1][a], h[s][1]);
+      t = cjmadd(t, u.e[2][a], h[s][2]);
+      w[s][a] = t;
+    }
+}
+
+// ------------------------------------------------------ solver scalars ----
+// Per right-hand-side scalar state of a CG run, kept in device memory so
+// that iterations can be enqueued back to back without host round trips.
+struct CgState {
+  double rho;     // <r, r> of the current residual
+  double alpha;   // step of the current iteration
+  double beta;    // direction update coefficient of the current iteration
+  double stop2;   // inner loop ends when rho < stop2
+  double res[2];  // result of the last plain reduction (re, im)
+  double coef[4]; // host-set coefficients for the linear-combination kernels
+  int iters;      // iterations completed in this run
+  int kmax;       // iteration cap of this run
+  int done;       // no more iterations for this right-hand side
+  int active;     // the iteration in flight updates this right-hand side
+  int status;     // DIRAC_OK / DIRAC_EBREAKDOWN
+  int pad[3];
+};
+
+enum FinalizeKind : int {
+  kFinPlain = 0,   // res = sum
+  kFinAlpha = 1,   // alpha = rho / sum (start of an iteration)
+  kFinRho = 2,     // rho_new = sum: beta, rho, iters, done
+  kFinRhoSet = 3,  // rho = sum (start of a run)
+};
+
+__device__ __forceinline__ void cg_finalize(CgState& st, int kind, double s0, double s1) {
+  if (kind == kFinPlain) {
+    st.res[0] = s0;
+    st.res[1] = s1;
+  } else if (kind == kFinRhoSet) {
+    st.rho = s0;
+    st.res[0] = s0;
+    st.res[1] = 0.0;
+  } else if (kind == kFinAlpha) {
+    if (st.done) {
+      st.active = 0;
+      st.alpha = 0.0;
+    } else if (!(s0 > 0.0) || !isfinite(s0) || !isfinite(st.rho)) {
+      st.active = 0;
+      st.alpha = 0.0;
+      st.done = 1;
+      st.status = DIRAC_EBREAKDOWN;
+    } else {
+      st.active = 1;
+      st.alpha = st.rho / s0;
+    }
+  } else if (kind == kFinRho) {
+    if (st.active) {
+      if (!isfinite(s0)) {
+        st.done = 1;
+        st.status = DIRAC_EBREAKDOWN;
+        st.beta = 0.0;
+      } else {
+        st.beta = s0 / st.rho;
+        st.rho = s0;
+      }
+      st.iters += 1;
+      if (st.rho < st.stop2 || st.iters >= st.kmax) st.done = 1;
+    }
+  }
+}
+
+// ---------------------------------------------- deterministic reduction ----
+// Each block reduces NC float64 values per right-hand side over its threads
+// (fixed order), writes them to partials[(rhs * nblocks + block) * NC + c],
+// and the last block to finish (found with one atomic counter) sums the
+// partials of every right-hand side in a fixed order and applies
+// cg_finalize.  The result therefore does not depend on block scheduling,
+// and the counter is left at zero for the next launch.
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct RedArgs {
+  double* partials;    // [nrhs][nparts][NC]
+  unsigned* counter;   // one per launch site, zero between launches
+  CgState* state;      // [nrhs], may be null for kFinPlain into res
+  int kind;
+};
+
+// vals[r][c] are this thread's contributions for right-hand side
+// rhs0 + r (r < RPT).  Threads are laid out [blockDim.y][blockDim.x], with
+// blockDim.x a multiple of 64 and every thread of a row sharing rhs0.
+// part/nparts: this block's slot among the nparts blocks that cover one
+// right-hand side; total_blocks: blocks in the launch (all of them arrive at
+// the counter).
+template <int RPT, int NC>
+__device__ void block_reduce_finalize(const RedArgs& ra, double (&vals)[RPT][NC], int rhs0,
+                                      int nrhs, int part, int nparts, int total_blocks) {
+  __shared__ double red[16][RPT * NC];
+  __shared__ int is_last;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int waves_per_row = blockDim.x >> 6;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double s = wave_sum(vals[r][c]);
+      if (lane == 0) red[wave][r * NC + c] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int r = 0; r < RPT; ++r) {
+      int rhs = rhs0 + r;
+      if (rhs >= nrhs) continue;
+      for (int c = 0; c < NC; ++c) {
+        double s = 0.0;
+        for (int w = 0; w < waves_per_row; ++w) s += red[threadIdx.y * waves_per_row + w][r * NC + c];
+        ra.partials[((size_t)rhs * nparts + part) * NC + c] = s;
+      }
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    unsigned prev = atomicAdd(ra.counter, 1u);
+    is_last = (prev == (unsigned)(total_blocks - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  // Last block: fixed-order sum per (rhs, c) with the block's threads.
+  __shared__ double tree[256];
+  const int nthr = blockDim.x * blockDim.y;
+  for (int rhs = 0; rhs < nrhs; ++rhs) {
+    double tot[NC];
+    for (int c = 0; c < NC; ++c) {
+      double s = 0.0;
+      if (tid < 256) {
+        for (int b = tid; b < nparts; b += (nthr < 256 ? nthr : 256))
+          s += __hip_atomic_load(&ra.partials[((size_t)rhs * nparts + b) * NC + c], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        tree[tid] = s;
+      }
+      __syncthreads();
+      const int n = nthr < 256 ? nthr : 256;
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w && tid + w < n) tree[tid] += tree[tid + w];
+        __syncthreads();
+      }
+      tot[c] = tree[0];
+      __syncthreads();
+    }
+    if (tid == 0) cg_finalize(ra.state[rhs], ra.kind, tot[0], NC > 1 ? tot[NC - 1] : 0.0);
+  }
+  if (tid == 0) *ra.counter = 0u;
+}
+
+}  // namespace dirac

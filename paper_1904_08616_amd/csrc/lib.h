@@ -1,0 +1,67 @@
+// Internal host-side interfaces shared by the C ABI (api.cpp), the solver
+// (solver.cpp) and the batched launches (multi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "dirac.h"
+#include "common.h"
+#include "dslash_impl.h"
+#include "field.h"
+
+namespace dirac {
+
+// Validated view of a dirac_op.
+struct OpInfo {
+  Geom g;
+  int prec, link, nrhs;
+  double m_q;
+  int64_t V;
+  uint32_t field_bytes;   // one field of this precision
+  int64_t field_stride;   // distance between right-hand sides (256-byte aligned)
+  uint32_t gauge_bytes;
+};
+
+int set_error(int code, const char* fmt, ...);
+void clear_error();
+int check_op(const dirac_op* op, OpInfo* out, const char* what);
+int hip_status(hipError_t e, const char* what);
+
+inline int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+FieldRef field_of(const OpInfo& o, const void* p);
+FieldRef field_as(const OpInfo& o, int prec, const void* p);  // same geometry, other precision
+
+// Launch configuration of the Dslash kernels.
+struct LaunchCfg {
+  int S;      // threads (sites) per block
+  int R;      // right-hand sides per thread
+  int remap;  // XCD-aware tile order
+  int lds;    // LDS neighbour staging (not used by this kernel family: 0)
+  int tuned;
+};
+LaunchCfg launch_cfg(const OpInfo& o);
+
+// Run one Dslash instance; returns DIRAC_EUNSUPPORTED if no such instance.
+int run_dslash(int pin, int pout, int link, int dag, int epi, const LaunchCfg& c, DslashArgs a,
+               hipStream_t st);
+
+DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out);
+
+// Library-owned device scratch for reductions of API calls (grown on
+// demand, one per device).
+struct Scratch {
+  double* partials;
+  unsigned* counter;
+  CgState* state;
+};
+int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out);
+
+// Multi-lattice persistent launch (multi.hip).
+int multi_apply(int n, const OpInfo* infos, const void* const* U, const void* const* psi, void* const* chi,
+                int dagger, hipStream_t st);
+
+}  // namespace dirac

@@ -1,0 +1,506 @@
+// Conjugate gradient on A = D^dagger D (the solve of Algorithm 1).
+//
+// Plain CG (inner_prec = F64) runs Algorithm 1's inner recurrence entirely
+// in float64:  q = A p;  alpha = rho / <p, q>;  x += alpha p;  r -= alpha q;
+// rho' = <r, r>;  p = r + (rho'/rho) p.  Per iteration this is three
+// kernels:
+//   1. t = D p, fused with |t|^2 = <p, A p>  -> alpha        (device)
+//   2. r -= alpha D^dag t, fused with |r|^2  -> beta, rho    (device)
+//      (A p itself is never stored)
+//   3. x += alpha p;  p = r + beta p
+// All scalars live in device memory (CgState), so a batch of iterations is
+// enqueued without host round trips; the host checks convergence between
+// batches.  Converged right-hand sides are gated off inside the kernels.
+// When the recursive residual reaches the target, the true residual
+// ||eta - A x|| is recomputed in float64 and the solve restarts from it if it
+// is still above the tolerance.
+//
+// Mixed precision (inner_prec = F32 / F16S / BF16S) follows Algorithm 1:
+// a float64 outer loop computes the true residual r = eta - A x, its norm
+// s, and the normalised r0 = r / s in low precision; a low-precision inner
+// CG (float32 arithmetic, float64 reductions) solves A psi = r0 until
+// ||r_inner|| < delta; the solution is updated x += s psi in float64.  The
+// search direction of the previous cycle is carried over after removing its
+// component along the new r0 and rescaling by beta_0 = s_new / (s_old rho_k)
+// (the reading of the carried direction p_0 = r0 + beta_0 p~).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lib.h"
+
+namespace dirac {
+
+namespace {
+
+struct Layout {
+  int64_t state, counter, partials, r, p, t, r0, psi, plo, tlo, total;
+  int64_t nparts;  // partial slots per right-hand side
+};
+
+Layout layout(const OpInfo& hi, int inner_prec) {
+  Layout L;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const int nrhs = hi.nrhs;
+  L.nparts = 2 * ((hi.g.Vh + 63) / 64);
+  L.state = take(sizeof(CgState) * kMaxRhs);
+  L.counter = take(256);
+  L.partials = take(L.nparts * nrhs * 2 * (int64_t)sizeof(double));
+  const int64_t f64 = nrhs * align256(spinor_field_bytes(DIRAC_F64, hi.V));
+  L.r = take(f64);
+  L.p = take(f64);
+  L.t = take(f64);
+  if (inner_prec != DIRAC_F64) {
+    const int64_t f32 = nrhs * align256(spinor_field_bytes(DIRAC_F32, hi.V));
+    const int64_t flo = nrhs * align256(spinor_field_bytes(inner_prec, hi.V));
+    L.r0 = take(f32);
+    L.psi = take(f32);
+    L.plo = take(flo);
+    L.tlo = take(flo);
+  } else {
+    L.r0 = L.psi = L.plo = L.tlo = -1;
+  }
+  L.total = off;
+  return L;
+}
+
+struct Ctx {
+  OpInfo hi, lo;
+  const void* Uhi;
+  const void* Ulo;
+  char* work;
+  Layout L;
+  hipStream_t st;
+  CgState* dstate;
+  std::vector<CgState> hstate;
+  RedTarget red(int kind) const {
+    return RedTarget{(double*)(work + L.partials), (unsigned*)(work + L.counter), dstate, kind};
+  }
+  FieldRef f(int64_t off, int prec) const { return field_as(hi, prec, work + off); }
+  int pull() {
+    int rc = hip_status(hipMemcpyAsync(hstate.data(), dstate, sizeof(CgState) * hi.nrhs, hipMemcpyDeviceToHost, st),
+                        "state readback");
+    if (rc != DIRAC_OK) return rc;
+    return hip_status(hipStreamSynchronize(st), "solver sync");
+  }
+  int push() {
+    int rc = hip_status(hipMemcpyAsync(dstate, hstate.data(), sizeof(CgState) * hi.nrhs, hipMemcpyHostToDevice, st),
+                        "state upload");
+    if (rc != DIRAC_OK) return rc;
+    return hip_status(hipStreamSynchronize(st), "solver sync");
+  }
+};
+
+RedArgs to_args(const RedTarget& t) { return RedArgs{t.partials, t.counter, t.state, t.kind}; }
+
+// sqrt of a reduced norm^2; NaN stays NaN (std::max would turn it into 0).
+double norm_of(double v) { return std::isnan(v) ? v : std::sqrt(v > 0.0 ? v : 0.0); }
+
+// t = D in (store + |t|^2 into `kind`), for precision op o.
+int dslash_norm(const Ctx& c, const OpInfo& o, const void* U, const void* in, void* t, int gate, int kind) {
+  DslashArgs a = dslash_args(o, U, in, t);
+  a.gate = gate;
+  a.red = to_args(c.red(kind));
+  return run_dslash(o.prec, o.prec, o.link, 0, kEpiStoreNorm, launch_cfg(o), a, c.st);
+}
+
+// dst = src - coef * D^dag in, |dst|^2 into `kind`; dst has precision dprec.
+int dslash_sub(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void* src, void* dst, int dprec,
+               int use_alpha, int gate, int kind) {
+  DslashArgs a = dslash_args(o, U, in, dst);
+  const FieldRef d = field_as(c.hi, dprec, dst);
+  a.out_bytes = d.bytes;
+  a.out_stride = d.stride;
+  a.src = (const char*)src;
+  a.src_stride = d.stride;
+  a.sub_alpha = use_alpha;
+  a.gate = gate;
+  a.red = to_args(c.red(kind));
+  return run_dslash(o.prec, dprec, o.link, 1, kEpiSubNorm, launch_cfg(o), a, c.st);
+}
+
+// r = eta - A x (float64), |r|^2 into `kind`.
+int true_residual(Ctx& c, const void* eta, const void* x, int kind) {
+  int rc = dslash_norm(c, c.hi, c.Uhi, x, c.work + c.L.t, kGateNone, kFinPlain);
+  if (rc != DIRAC_OK) return rc;
+  return dslash_sub(c, c.hi, c.Uhi, c.work + c.L.t, eta, c.work + c.L.r, DIRAC_F64, 0, kGateNone, kind);
+}
+
+int auto_check_every(const OpInfo& o) {
+  const double iter_us = std::max(15.0, o.V * o.nrhs * 6e-4);
+  return (int)std::min(64.0, std::max(2.0, std::round(600.0 / iter_us)));
+}
+
+// Run CG iterations on (x, p, r) with the given operator until every
+// right-hand side is done; returns iterations done per RHS via hstate.
+int run_iterations(Ctx& c, const OpInfo& o, const void* U, FieldRef x, FieldRef p, FieldRef r, FieldRef t,
+                   int check_every) {
+  while (true) {
+    for (int k = 0; k < check_every; ++k) {
+      int rc = dslash_norm(c, o, U, p.ptr, t.ptr, kGateNotDone, kFinAlpha);
+      if (rc != DIRAC_OK) return rc;
+      rc = dslash_sub(c, o, U, t.ptr, r.ptr, r.ptr, r.prec, 1, kGateActive, kFinRho);
+      if (rc != DIRAC_OK) return rc;
+      rc = hip_status(cg_xp_update(c.hi.g, c.hi.nrhs, x, p, r, c.dstate, c.st), "cg update");
+      if (rc != DIRAC_OK) return rc;
+    }
+    int rc = c.pull();
+    if (rc != DIRAC_OK) return rc;
+    bool all = true;
+    for (int k = 0; k < c.hi.nrhs; ++k) all &= c.hstate[k].done != 0;
+    if (all) return DIRAC_OK;
+  }
+}
+
+int eta_norms(Ctx& c, const void* eta, std::vector<double>& en) {
+  int rc = hip_status(norm2(c.hi.g, c.hi.nrhs, field_of(c.hi, eta), c.red(kFinPlain), c.st), "norm");
+  if (rc != DIRAC_OK) return rc;
+  rc = c.pull();
+  if (rc != DIRAC_OK) return rc;
+  for (int k = 0; k < c.hi.nrhs; ++k) en[k] = std::sqrt(c.hstate[k].res[0]);
+  return DIRAC_OK;
+}
+
+// Plain float64 CG starting from x (in place).
+int cg_f64(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::vector<double>& en,
+           std::vector<cg_stats>& stats, int check_every) {
+  const int n = c.hi.nrhs;
+  FieldRef X = field_of(c.hi, x), P = c.f(c.L.p, DIRAC_F64), R = c.f(c.L.r, DIRAC_F64), T = c.f(c.L.t, DIRAC_F64);
+  std::vector<int> used(n, 0);
+  std::vector<bool> finished(n, false);
+  for (int k = 0; k < n; ++k) {
+    used[k] = stats[k].iters;
+    if (en[k] == 0.0) finished[k] = true;
+    if (!std::isfinite(en[k])) {
+      stats[k].status = DIRAC_EBREAKDOWN;
+      finished[k] = true;
+    }
+  }
+  while (true) {
+    int rc = true_residual(c, eta, x, kFinRhoSet);
+    if (rc != DIRAC_OK) return rc;
+    for (int k = 0; k < n; ++k) stats[k].dslash_hi += 2;
+    rc = c.pull();
+    if (rc != DIRAC_OK) return rc;
+    bool any = false;
+    for (int k = 0; k < n; ++k) {
+      const double res = norm_of(c.hstate[k].rho);
+      const double rel = en[k] > 0 ? res / en[k] : 0.0;
+      if (!finished[k]) {
+        stats[k].true_rel_res = rel;
+        stats[k].outer += 1;
+        if (!std::isfinite(rel)) {
+          stats[k].status = DIRAC_EBREAKDOWN;
+          finished[k] = true;
+        } else if (rel < prm.tol) {
+          stats[k].status = DIRAC_OK;
+          finished[k] = true;
+        } else if (used[k] >= prm.max_iter) {
+          stats[k].status = DIRAC_ENOCONV;
+          finished[k] = true;
+        } else if (stats[k].status == DIRAC_EBREAKDOWN) {
+          finished[k] = true;
+        }
+      }
+      CgState& s = c.hstate[k];
+      s.stop2 = std::pow(prm.tol * en[k], 2);
+      s.kmax = std::max(0, prm.max_iter - used[k]);
+      s.iters = 0;
+      s.done = finished[k] ? 1 : 0;
+      s.active = 0;
+      s.status = DIRAC_OK;
+      any |= !finished[k];
+    }
+    if (!any) return DIRAC_OK;
+    rc = c.push();
+    if (rc != DIRAC_OK) return rc;
+    rc = hip_status(convert_scale(c.hi.g, n, R, P, nullptr, -1, nullptr, c.st), "copy");  // p = r
+    if (rc != DIRAC_OK) return rc;
+    rc = run_iterations(c, c.hi, c.Uhi, X, P, R, T, check_every);
+    if (rc != DIRAC_OK) return rc;
+    for (int k = 0; k < n; ++k) {
+      if (finished[k]) continue;
+      stats[k].iters += c.hstate[k].iters;
+      stats[k].dslash_hi += 2 * c.hstate[k].iters;
+      used[k] += c.hstate[k].iters;
+      if (c.hstate[k].status == DIRAC_EBREAKDOWN) stats[k].status = DIRAC_EBREAKDOWN;
+    }
+  }
+}
+
+// Algorithm 1 with a low-precision inner CG.
+int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::vector<double>& en,
+             std::vector<cg_stats>& stats, int check_every, bool* fallback) {
+  const int n = c.hi.nrhs;
+  const int lp = c.lo.prec;
+  FieldRef X = field_of(c.hi, x), R = c.f(c.L.r, DIRAC_F64);
+  FieldRef R0 = c.f(c.L.r0, DIRAC_F32), PSI = c.f(c.L.psi, DIRAC_F32), PLO = c.f(c.L.plo, lp),
+           TLO = c.f(c.L.tlo, lp);
+  const double delta = prm.inner_delta > 0 ? prm.inner_delta : (lp == DIRAC_F32 ? 1e-3 : 0.1);
+  const int kmax = prm.inner_kmax > 0 ? prm.inner_kmax : 10000;
+
+  std::vector<double> s(n), s_prev(n, 0.0), s_best(n), rho_k(n, 0.0);
+  std::vector<bool> have_p(n, false), conv(n, false);
+  std::vector<int> stall(n, 0), used(n, 0);
+  *fallback = false;
+
+  int rc = hip_status(zero(c.hi.g, n, PLO, c.st), "zero");
+  if (rc != DIRAC_OK) return rc;
+  rc = true_residual(c, eta, x, kFinPlain);
+  if (rc != DIRAC_OK) return rc;
+  rc = c.pull();
+  if (rc != DIRAC_OK) return rc;
+  for (int k = 0; k < n; ++k) {
+    stats[k].dslash_hi += 2;
+    s[k] = norm_of(c.hstate[k].res[0]);
+    s_best[k] = s[k];
+    conv[k] = en[k] == 0.0 || s[k] < prm.tol * en[k] || !std::isfinite(en[k]);
+    if (!std::isfinite(en[k])) stats[k].status = DIRAC_EBREAKDOWN;
+    stats[k].true_rel_res = en[k] > 0 ? s[k] / en[k] : 0.0;
+  }
+
+  while (true) {
+    bool any = false;
+    for (int k = 0; k < n; ++k) {
+      if (conv[k]) continue;
+      if (!std::isfinite(s[k])) {
+        stats[k].status = DIRAC_EBREAKDOWN;
+        conv[k] = true;
+        continue;
+      }
+      if (used[k] >= prm.max_iter) {
+        stats[k].status = DIRAC_ENOCONV;
+        conv[k] = true;
+        continue;
+      }
+      any = true;
+    }
+    if (!any) return DIRAC_OK;
+
+    // r0 = r / s in float32 (rho0 = |r0|^2 as stored), converged RHS scaled by 0
+    for (int k = 0; k < n; ++k) c.hstate[k].coef[0] = conv[k] ? 0.0 : 1.0 / s[k];
+    rc = c.push();
+    if (rc != DIRAC_OK) return rc;
+    RedTarget rt = c.red(kFinRhoSet);
+    rc = hip_status(convert_scale(c.hi.g, n, R, R0, c.dstate, 0, &rt, c.st), "cast");
+    if (rc != DIRAC_OK) return rc;
+    // carried direction: <r0, p_k>
+    rc = hip_status(dot(c.hi.g, n, R0, PLO, c.red(kFinPlain), c.st), "dot");
+    if (rc != DIRAC_OK) return rc;
+    rc = c.pull();
+    if (rc != DIRAC_OK) return rc;
+    for (int k = 0; k < n; ++k) {
+      CgState& S = c.hstate[k];
+      const double rho0 = S.rho;
+      if (have_p[k] && !conv[k] && rho0 > 0) {
+        // p0 = r0 + beta0 (p_k - (<r0,p_k>/rho0) r0) = (1 - beta0 c/rho0) r0 + beta0 p_k
+        const double beta0 = s[k] / (s_prev[k] * rho_k[k]);
+        S.coef[0] = 1.0 - beta0 * S.res[0] / rho0;
+        S.coef[1] = -beta0 * S.res[1] / rho0;
+        S.coef[2] = beta0;
+        S.coef[3] = 0.0;
+      } else {
+        S.coef[0] = 1.0;
+        S.coef[1] = 0.0;
+        S.coef[2] = 0.0;
+        S.coef[3] = 0.0;
+      }
+      const double stop_a = delta * delta;
+      const double stop_b = std::pow(0.5 * prm.tol * en[k] / std::max(s[k], 1e-300), 2);
+      S.stop2 = std::max(stop_a, stop_b);
+      S.kmax = std::max(1, std::min(kmax, prm.max_iter - used[k]));
+      S.iters = 0;
+      S.done = conv[k] ? 1 : 0;
+      S.active = 0;
+      S.status = DIRAC_OK;
+    }
+    rc = c.push();
+    if (rc != DIRAC_OK) return rc;
+    rc = hip_status(axpby(c.hi.g, n, R0, PLO, c.dstate, 0, 0, 0, 0, c.st), "restart direction");
+    if (rc != DIRAC_OK) return rc;
+    rc = hip_status(zero(c.hi.g, n, PSI, c.st), "zero");
+    if (rc != DIRAC_OK) return rc;
+
+    rc = run_iterations(c, c.lo, c.Ulo, PSI, PLO, R0, TLO, check_every);
+    if (rc != DIRAC_OK) return rc;
+    for (int k = 0; k < n; ++k) {
+      CgState& S = c.hstate[k];
+      if (conv[k]) continue;
+      stats[k].iters += S.iters;
+      stats[k].dslash_lo += 2 * S.iters;
+      used[k] += S.iters;
+      rho_k[k] = S.rho;
+      // x += s psi
+      S.coef[0] = s[k];
+      S.coef[1] = 0.0;
+      S.coef[2] = 1.0;
+      S.coef[3] = 0.0;
+    }
+    for (int k = 0; k < n; ++k)
+      if (conv[k]) {
+        c.hstate[k].coef[0] = 0.0;
+        c.hstate[k].coef[1] = 0.0;
+        c.hstate[k].coef[2] = 1.0;
+        c.hstate[k].coef[3] = 0.0;
+      }
+    rc = c.push();
+    if (rc != DIRAC_OK) return rc;
+    rc = hip_status(axpby(c.hi.g, n, PSI, X, c.dstate, 0, 0, 0, 0, c.st), "accumulate");
+    if (rc != DIRAC_OK) return rc;
+    rc = true_residual(c, eta, x, kFinPlain);
+    if (rc != DIRAC_OK) return rc;
+    rc = c.pull();
+    if (rc != DIRAC_OK) return rc;
+    bool stagnated = false;
+    for (int k = 0; k < n; ++k) {
+      if (conv[k]) continue;
+      stats[k].dslash_hi += 2;
+      stats[k].outer += 1;
+      s_prev[k] = s[k];
+      s[k] = norm_of(c.hstate[k].res[0]);
+      stats[k].true_rel_res = s[k] / en[k];
+      have_p[k] = true;
+      if (s[k] < prm.tol * en[k]) {
+        conv[k] = true;
+        stats[k].status = DIRAC_OK;
+        continue;
+      }
+      if (s[k] < s_best[k]) {
+        s_best[k] = s[k];
+        stall[k] = 0;
+      } else if (++stall[k] >= 3) {
+        have_p[k] = false;  // restart without the carried direction
+        if (stall[k] >= 6) stagnated = true;
+      }
+    }
+    if (stagnated) {
+      *fallback = true;  // finish in float64
+      return DIRAC_OK;
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace dirac
+
+using namespace dirac;
+
+extern "C" {
+
+int64_t cg_workspace_bytes(const dirac_op* op_hi, const cg_params* params) {
+  clear_error();
+  OpInfo hi;
+  int rc = check_op(op_hi, &hi, "cg_workspace_bytes");
+  if (rc != DIRAC_OK) return rc;
+  if (params == nullptr) return set_error(DIRAC_EINVAL, "cg_workspace_bytes: params is NULL");
+  const int ip = params->inner_prec;
+  if (ip != DIRAC_F64 && ip != DIRAC_F32 && ip != DIRAC_F16S && ip != DIRAC_BF16S)
+    return set_error(DIRAC_EINVAL, "cg_workspace_bytes: unknown inner_prec %d", ip);
+  return layout(hi, ip).total;
+}
+
+int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* eta, void* x, void* work,
+             int64_t work_bytes, const cg_params* params, cg_stats* stats_out, void* stream) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  OpInfo hi;
+  int rc = check_op(op_hi, &hi, "cg_solve");
+  if (rc != DIRAC_OK) return rc;
+  if (hi.prec != DIRAC_F64) return set_error(DIRAC_EINVAL, "cg_solve: op_hi must be DIRAC_F64");
+  if (params == nullptr || stats_out == nullptr) return set_error(DIRAC_EINVAL, "cg_solve: NULL params/stats");
+  cg_params prm = *params;
+  if (!(prm.tol > 0) || !std::isfinite(prm.tol)) return set_error(DIRAC_EINVAL, "cg_solve: tol must be > 0");
+  if (prm.max_iter < 1) return set_error(DIRAC_EINVAL, "cg_solve: max_iter must be >= 1");
+  if (!std::isfinite(prm.inner_delta)) return set_error(DIRAC_EINVAL, "cg_solve: inner_delta must be finite");
+  const int ip = prm.inner_prec;
+  if (ip != DIRAC_F64 && ip != DIRAC_F32 && ip != DIRAC_F16S && ip != DIRAC_BF16S)
+    return set_error(DIRAC_EINVAL, "cg_solve: unknown inner_prec %d", ip);
+  if (!U_hi || !eta || !x || !work) return set_error(DIRAC_EINVAL, "cg_solve: NULL buffer");
+  if (ip != DIRAC_F64 && !U_lo) return set_error(DIRAC_EINVAL, "cg_solve: U_lo is NULL for a mixed solve");
+  if ((((uintptr_t)U_hi | (uintptr_t)eta | (uintptr_t)x | (uintptr_t)work | (uintptr_t)U_lo) & 255u) != 0)
+    return set_error(DIRAC_EINVAL, "cg_solve: buffers must be 256-byte aligned");
+  Layout L = layout(hi, ip);
+  if (work_bytes < L.total)
+    return set_error(DIRAC_EWORKSPACE, "cg_solve: workspace needs %lld bytes, got %lld", (long long)L.total,
+                     (long long)work_bytes);
+  const int64_t sb = hi.nrhs * hi.field_stride;
+  auto ov = [](const void* a, int64_t na, const void* b, int64_t nb) {
+    const char* p = (const char*)a;
+    const char* q = (const char*)b;
+    return p < q + nb && q < p + na;
+  };
+  if (ov(eta, sb, x, sb) || ov(work, L.total, x, sb) || ov(work, L.total, eta, sb) ||
+      ov(work, L.total, U_hi, hi.gauge_bytes))
+    return set_error(DIRAC_EINVAL, "cg_solve: buffers overlap");
+
+  Ctx c;
+  c.hi = hi;
+  c.lo = hi;
+  if (ip != DIRAC_F64) {
+    dirac_op lo = *op_hi;
+    lo.prec = ip;
+    lo.link = (ip == DIRAC_F32) ? op_hi->link : DIRAC_LINK12;
+    rc = check_op(&lo, &c.lo, "cg_solve (inner)");
+    if (rc != DIRAC_OK) return rc;
+  }
+  c.Uhi = U_hi;
+  c.Ulo = U_lo;
+  c.work = (char*)work;
+  c.L = L;
+  c.st = (hipStream_t)stream;
+  c.dstate = (CgState*)(c.work + L.state);
+  c.hstate.assign(kMaxRhs, CgState{});
+  std::memset(c.hstate.data(), 0, sizeof(CgState) * kMaxRhs);
+  rc = hip_status(hipMemsetAsync(c.work + L.counter, 0, 256, c.st), "clear counter");
+  if (rc != DIRAC_OK) return rc;
+  rc = c.push();
+  if (rc != DIRAC_OK) return rc;
+
+  const int n = hi.nrhs;
+  std::vector<cg_stats> stats(n);
+  for (auto& s : stats) {
+    std::memset(&s, 0, sizeof(s));
+    s.status = DIRAC_ENOCONV;
+  }
+  const int check_every = prm.check_every > 0 ? prm.check_every : auto_check_every(ip == DIRAC_F64 ? hi : c.lo);
+  std::vector<double> en(n, 0.0);
+  rc = eta_norms(c, eta, en);
+  if (rc == DIRAC_OK) {
+    for (int k = 0; k < n; ++k)
+      if (!std::isfinite(en[k])) stats[k].status = DIRAC_EBREAKDOWN;
+  }
+  bool fallback = false;
+  if (rc == DIRAC_OK && ip != DIRAC_F64) rc = cg_mixed(c, eta, x, prm, en, stats, check_every, &fallback);
+  if (rc == DIRAC_OK && (ip == DIRAC_F64 || fallback)) {
+    for (auto& s : stats)
+      if (s.status != DIRAC_EBREAKDOWN) s.status = DIRAC_ENOCONV;
+    rc = cg_f64(c, eta, x, prm, en, stats, check_every);
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int overall = DIRAC_OK;
+  for (int k = 0; k < n; ++k) {
+    if (en[k] == 0.0 && stats[k].status != DIRAC_EBREAKDOWN) {
+      stats[k].status = DIRAC_OK;
+      stats[k].true_rel_res = 0.0;
+    }
+    stats[k].seconds = secs;
+    stats_out[k] = stats[k];
+    if (overall == DIRAC_OK && stats[k].status != DIRAC_OK) overall = stats[k].status;
+  }
+  if (rc != DIRAC_OK) return rc;
+  if (overall != DIRAC_OK)
+    set_error(overall, "cg_solve: not every right-hand side converged (first status %d)", overall);
+  return overall;
+}
+
+}  // extern "C"

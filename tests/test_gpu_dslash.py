@@ -1,0 +1,161 @@
+"""Parity of the HIP Dslash (eq. (1)) with the CPU oracle, through the C ABI.
+
+Bars: float64 max relative error (inf-norm over all components) <= 1e-13;
+float32 <= 5e-6 against the oracle on the same (rounded) inputs; scaled
+float16 / bfloat16 against the oracle on the rounded inputs, to the output
+rounding of the format."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lowprec, wilson
+from paper_1904_08616_amd import dirac as D
+from tests.gpu_helpers import at_sites, cuda, host, inputs, rel_inf, sample_sites
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [((2, 2, 2, 2), "haar"), ((4, 2, 6, 2), "haar"), ((4, 4, 4, 4), "haar"), ((6, 4, 2, 8), "exp"),
+         ((8, 8, 8, 8), "exp"), ((2, 10, 4, 6), "haar")]
+
+
+def _run(U, psi, m, prec, link, dagger, nrhs=None):
+    lt, lz, ly, lx = U.shape[:4]
+    op = D.Operator((lx, ly, lz, lt), m, prec, link, 1 if nrhs is None else nrhs)
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    out = op.unpack_spinor(op.apply(Ui, pi, dagger=dagger))
+    torch.cuda.synchronize()
+    return host(out)
+
+
+@pytest.mark.parametrize("dims,kind", SMALL)
+@pytest.mark.parametrize("link", [18, 12])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_f64_parity(dims, kind, link, dagger):
+    U, psi = inputs(dims, kind, seed=1)
+    m = 0.1
+    ref = (wilson.dslash_dagger if dagger else wilson.dslash)(U, psi, m)
+    got = _run(U, psi, m, "f64", link, dagger)
+    assert rel_inf(got, ref) <= 1e-13
+
+
+def test_f64_gamma5_hermiticity_on_gpu():
+    dims = (4, 2, 6, 2)
+    U, psi = inputs(dims, "haar", seed=2)
+    m = 0.05
+    g5 = np.diag([1.0, 1.0, -1.0, -1.0])
+    g5v = lambda v: np.einsum("ij,...jc->...ic", g5, v)
+    d = _run(U, g5v(psi), m, "f64", 18, False)
+    dd = _run(U, psi, m, "f64", 18, True)
+    assert rel_inf(g5v(d), dd) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,link,tol", [("f32", 18, 5e-6), ("f32", 12, 5e-6), ("f16s", 12, 1.5e-3),
+                                           ("bf16s", 12, 1.2e-2)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_low_precision_parity(prec, link, tol, dagger):
+    dims = (8, 4, 6, 4)
+    U, psi = inputs(dims, "exp", seed=3)
+    m = 0.05
+    # oracle on the inputs as the format stores them, in float64 arithmetic
+    Ur = lowprec.store_links(U, prec)
+    pr = lowprec.store(psi, prec)
+    ref = (wilson.dslash_dagger if dagger else wilson.dslash)(Ur, pr, m)
+    got = _run(U, psi, m, prec, link, dagger)
+    assert rel_inf(got, ref) <= tol
+    # and the error against the float64 oracle on the exact inputs, stated
+    exact = (wilson.dslash_dagger if dagger else wilson.dslash)(U, psi, m)
+    print(f"{prec}/{link}: err vs rounded-input oracle {rel_inf(got, ref):.2e}, "
+          f"vs exact-input oracle {rel_inf(got, exact):.2e}")
+
+
+def test_launch_configs_agree_bitwise_and_with_oracle():
+    # Candidates that differ only in block size and tile order run the same
+    # kernel, so they must agree bit for bit (a tile/race/mapping bug breaks
+    # this); every candidate must match the oracle.
+    dims = (4, 2, 6, 2)
+    nrhs = 5
+    U, psi = inputs(dims, "haar", seed=4, nrhs=nrhs)
+    m = 0.1
+    op = D.Operator(dims, m, "f64", 18, nrhs)
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    ref = np.stack([wilson.dslash(U, psi[k], m) for k in range(nrhs)])
+    for R in (1, 2, 3, 4):
+        first = None
+        for S in (64, 128, 256):
+            for remap in (0, 1):
+                op.set_launch_config(S, R, remap)
+                got = host(op.unpack_spinor(op.apply(Ui, pi)))
+                assert rel_inf(got, ref) <= 1e-13, (S, remap, R)
+                if first is None:
+                    first = got
+                else:
+                    assert np.array_equal(got, first), (S, remap, R)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_multi_rhs_point_sources(prec):
+    # 12 spin-colour point sources: column k equals the single-RHS result.
+    dims = (8, 8, 4, 6)
+    g = synth.rng(5)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)
+    m = 0.05
+    got = _run(U, src, m, prec, 12, False, nrhs=12)
+    for k in (0, 5, 11):
+        single = _run(U, src[k], m, prec, 12, False)
+        assert rel_inf(got[k], single) <= (1e-6 if prec == "f32" else 1e-3)
+    ref = np.stack([wilson.dslash(lowprec.store_links(U, prec), src[k], m) for k in range(12)])
+    assert rel_inf(got, ref) <= (5e-6 if prec == "f32" else 1.5e-3)
+
+
+def test_pack_roundtrips():
+    dims = (4, 2, 6, 2)
+    U, psi = inputs(dims, "haar", seed=6)
+    psi = psi * 10.0 ** synth.rng(7).uniform(-20, 20, size=psi.shape[:4])[..., None, None]
+    for prec in ("f64", "f32", "f16s", "bf16s"):
+        op = D.Operator(dims, 0.1, prec, 12)
+        back = host(op.unpack_spinor(op.pack_spinor(cuda(psi))))
+        if prec == "f64":
+            assert np.array_equal(back, psi)
+        elif prec == "f32":
+            assert np.array_equal(back, psi.astype(np.complex64).astype(np.complex128))
+        else:
+            ref = lowprec.store(psi, prec)
+            s = lowprec.site_scale(psi)[..., None, None]
+            ulp = 2.0 ** (-11 if prec == "f16s" else -8)
+            err = np.maximum(np.abs((back - ref).real), np.abs((back - ref).imag))
+            assert np.all(err <= ulp * s * 1.0001)
+
+
+def test_full_size_16x16x16x32_f64():
+    # configuration: 16^3 x 32, exp(i 0.3 H) links, m = 0.05, 18- and 12-real
+    dims = (16, 16, 16, 32)
+    U, psi = inputs(dims, "exp", seed=0)
+    m = 0.05
+    ref = wilson.dslash(U, psi, m)
+    for link in (18, 12):
+        got = _run(U, psi, m, "f64", link, False)
+        assert rel_inf(got, ref) <= 1e-13
+
+
+def test_full_size_32x32x32x64_sampled():
+    # configuration: 32^3 x 64, exp(i 0.3 H) links, m = 0.02; float64 on a
+    # sample of sites (and every corner), float32 / float16s likewise.
+    dims = (32, 32, 32, 64)
+    U, psi = inputs(dims, "exp", seed=0)
+    m = 0.02
+    sites = sample_sites(dims, 2000)
+    ref = wilson.dslash_at(U, psi, m, sites)
+    Uc, pc = cuda(U), cuda(psi)
+    for prec, link, tol in (("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6)):
+        op = D.Operator(dims, m, prec, link)
+        out = host(op.unpack_spinor(op.apply(op.pack_gauge(Uc), op.pack_spinor(pc))))
+        got = out[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
+        err = rel_inf(got, ref)
+        print(f"32^3x64 {prec}/{link}: sampled err {err:.2e}")
+        assert err <= tol
+        del out

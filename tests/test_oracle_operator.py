@@ -197,3 +197,17 @@ def test_ddagd_positive_and_linear():
     c = 0.3 - 1.7j
     lin = wilson.dslash(U, a + c * b, m)
     assert rel_inf(lin, wilson.dslash(U, a, m) + c * wilson.dslash(U, b, m)) < 1e-14
+
+
+def test_dslash_at_matches_full():
+    dims = (4, 2, 6, 2)
+    g = synth.rng(13)
+    U = synth.links_haar(dims, g)
+    psi = synth.spinor_gauss(dims, g)
+    m = 0.07
+    lx, ly, lz, lt = dims
+    sites = np.array([(x, y, z, t) for t in range(lt) for z in range(lz) for y in range(ly) for x in range(lx)])
+    full = wilson.dslash(U, psi, m).reshape(-1, 4, 3)
+    assert rel_inf(wilson.dslash_at(U, psi, m, sites), full) < 1e-14
+    fulld = wilson.dslash_dagger(U, psi, m).reshape(-1, 4, 3)
+    assert rel_inf(wilson.dslash_at(U, psi, m, sites, dagger=True), fulld) < 1e-14
