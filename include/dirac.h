@@ -216,26 +216,45 @@ int dirac_multi_plan_create(int32_t n, const dirac_op* ops, const void* const* U
 int dirac_plan_launch(void* plan, void* stream);
 int dirac_plan_destroy(void* plan);
 
-/* Time the Dslash launch candidates (threads per block, right-hand sides
- * per thread, XCD-aware tile order on/off, LDS staging on/off) for this op
- * on the given buffers with HIP events, and remember the fastest for every
- * later call with the same (device, geometry, precision, links, nrhs).
- * chi_int is overwritten.  Synchronises the stream.
- * If the environment variable DIRAC_TUNE_CACHE names a file, results are
- * appended there and read back by later processes. */
+/* Launch configuration of the Dslash kernels for one op.  Three kernel
+ * families compute the same per-site arithmetic (eq. (1)):
+ *   - one thread per site (lds = 0, rhs_per_thread 1..4): block_sites
+ *     threads per block, each thread doing rhs_per_thread right-hand sides
+ *     with one load of each link;
+ *   - direction split (lds = 0, rhs_per_thread -2 or -4): 2 or 4 waves share
+ *     each block of 64 sites, one direction pair per wave, partial spinors
+ *     combined in LDS (nrhs = 1; for lattices too small to fill the device);
+ *   - t-streaming (lds = 1): a block owns all of x times tile_y rows times
+ *     tile_z planes (128 or 256 columns) and walks t_chunk time slices; the
+ *     current slice is staged in LDS and the t neighbours stay in registers
+ *     (nrhs = 1; tile_y | Ly and tile_z | Lz).
+ * xcd_remap orders tiles so that each XCD sweeps one contiguous region;
+ * nt_store writes the output with non-temporal stores. */
+typedef struct dirac_launch {
+  int32_t block_sites;
+  int32_t rhs_per_thread;
+  int32_t xcd_remap;
+  int32_t nt_store;
+  int32_t lds;
+  int32_t tile_y, tile_z, t_chunk;
+  int32_t tuned; /* out only: 1 when chosen by the autotuner or set explicitly */
+} dirac_launch;
+
+/* Time every launch candidate above that fits this op on the given buffers
+ * with HIP events and remember the fastest for every later call with the
+ * same (device, geometry, precision, links, nrhs).  chi_int is overwritten.
+ * Synchronises the stream.  If the environment variable DIRAC_TUNE_CACHE
+ * names a file, results are appended there and read back by later
+ * processes. */
 int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int,
                    void* stream);
 
-/* The launch configuration the next dirac_apply with this op will use
- * (host out-params); tuned != 0 when it came from the autotuner. */
-int dirac_launch_config(const dirac_op* op, int32_t* block_sites, int32_t* rhs_per_thread,
-                        int32_t* xcd_remap, int32_t* lds, int32_t* tuned);
+/* The launch configuration the next call with this op will use (host out). */
+int dirac_launch_config(const dirac_op* op, dirac_launch* out);
 
-/* Force the launch configuration used for this op (for tests and expert
- * tuning): block_sites in {64, 128, 256}, rhs_per_thread in 1..4,
- * xcd_remap 0/1, lds must be 0. */
-int dirac_set_launch_config(const dirac_op* op, int32_t block_sites, int32_t rhs_per_thread,
-                            int32_t xcd_remap, int32_t lds);
+/* Force the launch configuration for this op (tests, expert tuning).
+ * EINVAL when it does not fit the op (see dirac_launch). */
+int dirac_set_launch_config(const dirac_op* op, const dirac_launch* cfg);
 
 /* Description of the last error on the calling host thread ("" if none). */
 const char* dirac_last_error(void);

@@ -26,6 +26,15 @@ class DiracOp(C.Structure):
                 ("nrhs", C.c_int32), ("flags", C.c_int32), ("m_q", C.c_double)]
 
 
+class DiracLaunch(C.Structure):
+    _fields_ = [("block_sites", C.c_int32), ("rhs_per_thread", C.c_int32), ("xcd_remap", C.c_int32),
+                ("nt_store", C.c_int32), ("lds", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
+                ("t_chunk", C.c_int32), ("tuned", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class CgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("inner_prec", C.c_int32),
                 ("inner_delta", C.c_double), ("inner_kmax", C.c_int32), ("check_every", C.c_int32)]
@@ -67,8 +76,8 @@ SIGNATURES = {
     "dirac_plan_launch": (C.c_int, [_P, _P]),
     "dirac_plan_destroy": (C.c_int, [_P]),
     "dirac_autotune": (C.c_int, [_OP, _P, _P, _P, _P]),
-    "dirac_launch_config": (C.c_int, [_OP] + [C.POINTER(C.c_int32)] * 5),
-    "dirac_set_launch_config": (C.c_int, [_OP, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "dirac_launch_config": (C.c_int, [_OP, C.POINTER(DiracLaunch)]),
+    "dirac_set_launch_config": (C.c_int, [_OP, C.POINTER(DiracLaunch)]),
     "dirac_last_error": (C.c_char_p, []),
     "dirac_version": (C.c_char_p, []),
 }

@@ -109,14 +109,21 @@ static std::vector<DslashEntry>& dslash_entries() {
 
 int run_dslash(int pin, int pout, int link, int dag, int epi, const LaunchCfg& c, DslashArgs a,
                hipStream_t st) {
+  // the streaming kernel takes one right-hand side on tiles that divide the lattice
+  const bool stream = c.lds && a.nrhs == 1 && stream_fits(a.g, c.sy, c.sz, c.tc);
+  const int key = stream ? 0 : (c.lds ? 1 : c.R);
   for (const DslashEntry& e : dslash_entries()) {
-    if (e.pin == pin && e.pout == pout && e.link == link && e.dag == dag && e.epi == epi && e.rpt == c.R) {
+    if (e.pin == pin && e.pout == pout && e.link == link && e.dag == dag && e.epi == epi && e.rpt == key) {
       a.remap = c.remap;
-      return hip_status(e.fn(a, c.S, st), "dslash launch");
+      a.nt_store = c.nt;
+      a.sy = c.sy;
+      a.sz = c.sz;
+      a.tc = c.tc;
+      return hip_status(e.fn(a, c.lds && !stream ? 128 : c.S, st), "dslash launch");
     }
   }
   return set_error(DIRAC_EUNSUPPORTED, "no Dslash kernel for prec %d->%d link %d dag %d epilogue %d R %d",
-                   pin, pout, link, dag, epi, c.R);
+                   pin, pout, link, dag, epi, key);
 }
 
 DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out) {
@@ -174,7 +181,8 @@ void load_cache_file_locked() {
   if (!f) return;
   char key[256];
   LaunchCfg c;
-  while (std::fscanf(f, "%255s %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds) == 5) {
+  while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds, &c.nt, &c.sy, &c.sz,
+                     &c.tc) == 9) {
     c.tuned = 1;
     g_cfg[key] = c;
   }
@@ -186,6 +194,8 @@ LaunchCfg default_cfg(const OpInfo& o) {
   c.S = 256;
   c.remap = 1;
   c.lds = 0;
+  c.nt = 0;
+  c.sy = c.sz = c.tc = 1;
   c.tuned = 0;
   if (o.nrhs == 1)
     c.R = 1;
@@ -213,7 +223,7 @@ static void store_cfg(const OpInfo& o, const LaunchCfg& c, bool to_file) {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c.S, c.R, c.remap, c.lds);
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d\n", key.c_str(), c.S, c.R, c.remap, c.lds, c.nt, c.sy, c.sz, c.tc);
   std::fclose(f);
 }
 
@@ -222,7 +232,6 @@ namespace {
 struct DevScratch {
   double* partials = nullptr;
   int64_t partial_cap = 0;
-  unsigned* counter = nullptr;
   CgState* state = nullptr;
 };
 std::mutex g_scratch_mu;
@@ -234,9 +243,7 @@ int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out) {
   if (hipGetDevice(&dev) != hipSuccess) return set_error(DIRAC_EDEVICE, "hipGetDevice failed");
   std::lock_guard<std::mutex> lk(g_scratch_mu);
   DevScratch& s = g_scratch[dev];
-  if (s.counter == nullptr) {
-    if (hipMalloc(&s.counter, 256) != hipSuccess) return set_error(DIRAC_EDEVICE, "scratch allocation failed");
-    if (hipMemset(s.counter, 0, 256) != hipSuccess) return set_error(DIRAC_EDEVICE, "scratch clear failed");
+  if (s.state == nullptr) {
     if (hipMalloc(&s.state, sizeof(CgState) * kMaxRhs) != hipSuccess)
       return set_error(DIRAC_EDEVICE, "scratch allocation failed");
     if (hipMemset(s.state, 0, sizeof(CgState) * kMaxRhs) != hipSuccess)
@@ -257,7 +264,6 @@ int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out) {
   }
   (void)nrhs;
   out->partials = s.partials;
-  out->counter = s.counter;
   out->state = s.state;
   return DIRAC_OK;
 }
@@ -416,7 +422,7 @@ int dirac_field_dot(const dirac_op* op, const void* a, const void* b, double* ou
   const int64_t nparts = 2 * ((o.g.Vh + 255) / 256);
   CHECK(lib_scratch(nparts * o.nrhs * 2, o.nrhs, &s));
   hipStream_t st = (hipStream_t)stream;
-  RedTarget red{s.partials, s.counter, s.state, kFinPlain};
+  RedTarget red{s.partials, s.state, kFinPlain};
   CHECK(hip_status(dot(o.g, o.nrhs, field_of(o, a), field_of(o, b), red, st), "dot"));
   std::vector<CgState> hs(o.nrhs);
   CHECK(hip_status(hipMemcpyAsync(hs.data(), s.state, sizeof(CgState) * o.nrhs, hipMemcpyDeviceToHost, st),
@@ -539,6 +545,28 @@ int dirac_plan_destroy(void* plan) {
 }
 
 // ------------------------------------------------------------ tuning -----
+// Streaming-kernel tiles worth timing for this geometry: all of x, tile_y x
+// tile_z chosen so the tile has 128 or 256 columns.
+static std::vector<LaunchCfg> stream_candidates(const OpInfo& o) {
+  std::vector<LaunchCfg> v;
+  if (o.nrhs != 1) return v;
+  for (int cols : {128, 256}) {
+    if (cols % o.g.X) continue;
+    const int yz = cols / o.g.X;
+    for (int sy = 1; sy <= yz; sy *= 2) {
+      const int sz = yz / sy;
+      if (sy * sz != yz) continue;
+      for (int tc : {1, 2, 4, 8, 16}) {
+        if (tc > o.g.T) continue;
+        if (!stream_fits(o.g, sy, sz, tc)) continue;
+        LaunchCfg c{64, 1, 1, 1, 0, sy, sz, tc, 1};
+        v.push_back(c);
+      }
+    }
+  }
+  return v;
+}
+
 int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int, void* stream) {
   clear_error();
   OpInfo o;
@@ -556,64 +584,94 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
   // Enough launches to be well above the timer resolution.
   const double est_us = std::max(5.0, o.V * 1e-4);
   const int reps = (int)std::min(200.0, std::max(5.0, 2000.0 / est_us));
+  std::vector<LaunchCfg> cands;
+  for (int S : {64, 128, 256})
+    for (int remap : {0, 1})
+      for (int nt : {0, 1})
+        for (int R = (o.nrhs == 1 ? -4 : 1); R <= std::min(4, o.nrhs); ++R) {
+          if (o.nrhs > 4 && R == 1) continue;
+          if (R == 0 || R == -1 || R == -3) continue;
+          if (R < 0 && S != 64) continue;  // the split kernel has fixed 64-site blocks
+          cands.push_back(LaunchCfg{S, R, remap, 0, nt, 1, 1, 1, 1});
+        }
+  for (const LaunchCfg& c0 : stream_candidates(o))
+    for (int remap : {0, 1})
+      for (int nt : {0, 1}) {
+        LaunchCfg c = c0;
+        c.remap = remap;
+        c.nt = nt;
+        cands.push_back(c);
+      }
   LaunchCfg best{};
   float best_ms = 1e30f;
   int rc = DIRAC_OK;
-  for (int S : {64, 128, 256}) {
-    for (int remap : {0, 1}) {
-      for (int R = 1; R <= std::min(4, o.nrhs); ++R) {
-        if (o.nrhs > 1 && R == 1 && o.nrhs > 4) continue;
-        LaunchCfg c{S, R, remap, 0, 1};
-        rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
-        if (rc != DIRAC_OK) break;
-        rc = hip_status(hipEventRecord(e0, st), "event record");
-        for (int k = 0; k < reps && rc == DIRAC_OK; ++k) rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
-        if (rc == DIRAC_OK) rc = hip_status(hipEventRecord(e1, st), "event record");
-        if (rc == DIRAC_OK) rc = hip_status(hipEventSynchronize(e1), "event sync");
-        if (rc != DIRAC_OK) break;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = c;
-        }
-      }
-      if (rc != DIRAC_OK) break;
-    }
+  for (const LaunchCfg& c : cands) {
+    rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
     if (rc != DIRAC_OK) break;
+    rc = hip_status(hipEventRecord(e0, st), "event record");
+    for (int k = 0; k < reps && rc == DIRAC_OK; ++k) rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
+    if (rc == DIRAC_OK) rc = hip_status(hipEventRecord(e1, st), "event record");
+    if (rc == DIRAC_OK) rc = hip_status(hipEventSynchronize(e1), "event sync");
+    if (rc != DIRAC_OK) break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != DIRAC_OK) return rc;
+  best.tuned = 1;
   store_cfg(o, best, true);
   return DIRAC_OK;
 }
 
-int dirac_launch_config(const dirac_op* op, int32_t* block_sites, int32_t* rhs_per_thread, int32_t* xcd_remap,
-                        int32_t* lds, int32_t* tuned) {
+int dirac_launch_config(const dirac_op* op, dirac_launch* out) {
   clear_error();
   OpInfo o;
   CHECK(check_op(op, &o, "dirac_launch_config"));
+  if (out == nullptr) return set_error(DIRAC_EINVAL, "dirac_launch_config: out is NULL");
   LaunchCfg c = launch_cfg(o);
-  if (block_sites) *block_sites = c.S;
-  if (rhs_per_thread) *rhs_per_thread = c.R;
-  if (xcd_remap) *xcd_remap = c.remap;
-  if (lds) *lds = c.lds;
-  if (tuned) *tuned = c.tuned;
+  out->block_sites = c.S;
+  out->rhs_per_thread = c.R;
+  out->xcd_remap = c.remap;
+  out->nt_store = c.nt;
+  out->lds = c.lds;
+  out->tile_y = c.sy;
+  out->tile_z = c.sz;
+  out->t_chunk = c.tc;
+  out->tuned = c.tuned;
   return DIRAC_OK;
 }
 
-int dirac_set_launch_config(const dirac_op* op, int32_t block_sites, int32_t rhs_per_thread, int32_t xcd_remap,
-                            int32_t lds) {
+int dirac_set_launch_config(const dirac_op* op, const dirac_launch* cfg) {
   clear_error();
   OpInfo o;
   CHECK(check_op(op, &o, "dirac_set_launch_config"));
-  if (block_sites != 64 && block_sites != 128 && block_sites != 256)
-    return set_error(DIRAC_EINVAL, "dirac_set_launch_config: block_sites must be 64, 128 or 256");
-  if (rhs_per_thread < 1 || rhs_per_thread > 4)
-    return set_error(DIRAC_EINVAL, "dirac_set_launch_config: rhs_per_thread must be 1..4");
-  if (lds != 0) return set_error(DIRAC_EUNSUPPORTED, "dirac_set_launch_config: lds staging is not built");
-  LaunchCfg c{block_sites, rhs_per_thread, xcd_remap ? 1 : 0, 0, 1};
+  if (cfg == nullptr) return set_error(DIRAC_EINVAL, "dirac_set_launch_config: cfg is NULL");
+  LaunchCfg c{cfg->block_sites, cfg->rhs_per_thread, cfg->xcd_remap ? 1 : 0, cfg->lds ? 1 : 0,
+              cfg->nt_store ? 1 : 0, cfg->tile_y, cfg->tile_z, cfg->t_chunk, 1};
+  if (c.lds) {
+    if (o.nrhs != 1) return set_error(DIRAC_EINVAL, "dirac_set_launch_config: the streaming kernel takes nrhs = 1");
+    if (!stream_fits(o.g, c.sy, c.sz, c.tc))
+      return set_error(DIRAC_EINVAL,
+                       "dirac_set_launch_config: tile %d x %d x %d (x, y, z) must divide the lattice and have "
+                       "128 or 256 columns, t_chunk >= 1",
+                       o.g.X, c.sy, c.sz);
+    c.S = 64;
+    c.R = 1;
+  } else {
+    if (c.S != 64 && c.S != 128 && c.S != 256)
+      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: block_sites must be 64, 128 or 256");
+    const bool split = c.R == -2 || c.R == -4;
+    if (!split && (c.R < 1 || c.R > 4))
+      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: rhs_per_thread must be 1..4, or -2/-4 (split)");
+    if (split && o.nrhs != 1)
+      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: the direction-split kernel takes nrhs = 1");
+    c.sy = c.sz = c.tc = 1;
+  }
   store_cfg(o, c, false);
   return DIRAC_OK;
 }

@@ -192,15 +192,17 @@ __device__ __forceinline__ T bld(Rsrc r, uint32_t voff, uint32_t soff) {
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
 }
-template <class T>
+// AUX = 0: ordinary store; AUX = 2: non-temporal (streaming) store that does
+// not keep the line in the L2.
+template <int AUX = 0, class T>
 __device__ __forceinline__ void bst(Rsrc r, uint32_t voff, uint32_t soff, const T& v) {
   static_assert(sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4, "buffer store size");
   if constexpr (sizeof(T) == 16) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, AUX);
   } else if constexpr (sizeof(T) == 8) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, AUX);
   }
 }
 
@@ -210,21 +212,43 @@ template <> struct SpinFmt<DIRAC_F64> {
   static constexpr bool kScaled = false;
   static constexpr int kSiteBytes = 192;
   __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      double2 t = bld<double2>(f, o, base + (uint32_t)c * (uint32_t)Vh * 16u);
+      double2 t = bld<double2>(f, o, (uint32_t)c * (uint32_t)Vh * 16u);
       v[c] = {t.x, t.y};
     }
   }
   __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
+  template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int c = 0; c < 12; ++c)
-      bst(f, o, base + (uint32_t)c * (uint32_t)Vh * 16u, make_double2(v[c].re, v[c].im));
+      bst<AUX>(f, o, (uint32_t)c * (uint32_t)Vh * 16u, make_double2(v[c].re, v[c].im));
+  }
+  // Store only the storage vectors [v0, v1) (vector k holds component k).
+  template <int AUX = 0>
+  __device__ static __forceinline__ void store_range(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
+                                                     int v0, int v1) {
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c)
+      if (c >= v0 && c < v1)
+        bst<AUX>(f, o, (uint32_t)c * (uint32_t)Vh * 16u, make_double2(v[c].re, v[c].im));
+  }
+  // Load only the storage vectors [v0, v1); other components are zero.
+  __device__ static __forceinline__ void load_range(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12], int v0,
+                                                    int v1) {
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      v[c] = {0.0, 0.0};
+      if (c >= v0 && c < v1) {
+        double2 t = bld<double2>(f, o, (uint32_t)c * (uint32_t)Vh * 16u);
+        v[c] = {t.x, t.y};
+      }
+    }
   }
 };
 
@@ -234,23 +258,48 @@ template <> struct SpinFmt<DIRAC_F32> {
   static constexpr bool kScaled = false;
   static constexpr int kSiteBytes = 96;
   __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 t = bld<float4>(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
+      float4 t = bld<float4>(f, o, (uint32_t)k * (uint32_t)Vh * 16u);
       v[2 * k] = {t.x, t.y};
       v[2 * k + 1] = {t.z, t.w};
     }
   }
   __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
+  template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < 6; ++k)
-      bst(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u,
-          make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
+      bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u,
+               make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
+  }
+  // Load only the storage vectors [v0, v1); other components are zero.
+  __device__ static __forceinline__ void load_range(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12], int v0,
+                                                    int v1) {
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      v[2 * k] = {0.f, 0.f};
+      v[2 * k + 1] = {0.f, 0.f};
+      if (k >= v0 && k < v1) {
+        float4 t = bld<float4>(f, o, (uint32_t)k * (uint32_t)Vh * 16u);
+        v[2 * k] = {t.x, t.y};
+        v[2 * k + 1] = {t.z, t.w};
+      }
+    }
+  }
+  // Store only the storage vectors [v0, v1) (vector k holds components 2k, 2k+1).
+  template <int AUX = 0>
+  __device__ static __forceinline__ void store_range(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
+                                                     int v0, int v1) {
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (k >= v0 && k < v1)
+        bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u,
+                 make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
   }
 };
 
@@ -266,12 +315,11 @@ template <bool BF> struct SpinScaled {
     return (uint32_t)Vh * 96u + (uint32_t)p * (uint32_t)Vh * 4u;
   }
   __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
-    const float s = bld<float>(f, (uint32_t)i * 4u, scale_off(Vh, p));
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
+    const float s = bld<float>(f, (uint32_t)i * 4u + scale_off(Vh, p), 0u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint4 t = bld<uint4>(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
+      uint4 t = bld<uint4>(f, o, (uint32_t)k * (uint32_t)Vh * 16u);
       unsigned w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -289,12 +337,12 @@ template <bool BF> struct SpinScaled {
       v[c].im = (m > 0.f) ? m * dec(enc(v[c].im / m)) : 0.f;
     }
   }
+  template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       unsigned w[4];
@@ -305,9 +353,9 @@ template <bool BF> struct SpinScaled {
         float im = (m > 0.f) ? v[4 * k + j].im / m : 0.f;
         w[j] = (unsigned)enc(re) | ((unsigned)enc(im) << 16);
       }
-      bst(f, o, base + (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));
+      bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));
     }
-    bst(f, (uint32_t)i * 4u, scale_off(Vh, p), m);
+    bst<AUX>(f, (uint32_t)i * 4u + scale_off(Vh, p), 0u, m);
   }
 };
 template <> struct SpinFmt<DIRAC_F16S> : SpinScaled<false> {};
@@ -334,8 +382,8 @@ template <int LK> struct LinkF64 {
   static constexpr int NL = LK / 2;
   static constexpr int kBytes = LK * 8;
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)((p * 4 + mu) * NL) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 4 * NL) * (uint32_t)Vh * 16u;
+    const uint32_t base = (uint32_t)(mu * NL) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
       double2 t = bld<double2>(U, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
@@ -352,8 +400,8 @@ template <> struct LinkFmt<DIRAC_F32, 18> {
   static constexpr int NL = 9;
   static constexpr int kBytes = 72;
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 8u;
-    const uint32_t base = (uint32_t)((p * 4 + mu) * 9) * (uint32_t)Vh * 8u;
+    const uint32_t o = (uint32_t)i * 8u + (uint32_t)(p * 4 * 9) * (uint32_t)Vh * 8u;
+    const uint32_t base = (uint32_t)(mu * 9) * (uint32_t)Vh * 8u;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       float2 t = bld<float2>(U, o, base + (uint32_t)k * (uint32_t)Vh * 8u);
@@ -366,8 +414,8 @@ template <> struct LinkFmt<DIRAC_F32, 12> {
   static constexpr int NL = 3;
   static constexpr int kBytes = 48;
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 16u;
-    const uint32_t base = (uint32_t)((p * 4 + mu) * 3) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 4 * 3) * (uint32_t)Vh * 16u;
+    const uint32_t base = (uint32_t)(mu * 3) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       float4 t = bld<float4>(U, o, base + (uint32_t)k * (uint32_t)Vh * 16u);
@@ -383,8 +431,8 @@ template <bool BF> struct LinkHalf12 {
   static constexpr int kBytes = 24;
   __device__ static __forceinline__ float dec(unsigned short h) { return BF ? bf16_to_f(h) : h_to_f(h); }
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 8u;
-    const uint32_t base = (uint32_t)((p * 4 + mu) * 3) * (uint32_t)Vh * 8u;
+    const uint32_t o = (uint32_t)i * 8u + (uint32_t)(p * 4 * 3) * (uint32_t)Vh * 8u;
+    const uint32_t base = (uint32_t)(mu * 3) * (uint32_t)Vh * 8u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       uint2 t = bld<uint2>(U, o, base + (uint32_t)k * (uint32_t)Vh * 8u);
@@ -555,12 +603,13 @@ __device__ __forceinline__ void cg_finalize(CgState& st, int kind, double s0, do
 }
 
 // ---------------------------------------------- deterministic reduction ----
-// Each block reduces NC float64 values per right-hand side over its threads
-// (fixed order), writes them to partials[(rhs * nblocks + block) * NC + c],
-// and the last block to finish (found with one atomic counter) sums the
-// partials of every right-hand side in a fixed order and applies
-// cg_finalize.  The result therefore does not depend on block scheduling,
-// and the counter is left at zero for the next launch.
+// Two stages, both in a fixed order: each block reduces NC float64 values per
+// right-hand side over its threads and stores them to
+// partials[(rhs * nparts + part) * NC + c]; a second kernel (k_finalize, one
+// block per right-hand side) sums the partials and applies cg_finalize.  The
+// kernel boundary between the stages makes the partials visible; no atomics
+// and no device-scope fences are needed (on a multi-XCD device a device-scope
+// release fence in every block would write back the L2 each time).
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -570,25 +619,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 struct RedArgs {
   double* partials;    // [nrhs][nparts][NC]
-  unsigned* counter;   // one per launch site, zero between launches
-  CgState* state;      // [nrhs], may be null for kFinPlain into res
+  CgState* state;      // [nrhs]
   int kind;
 };
 
-// vals[r][c] are this thread's contributions for right-hand side
-// rhs0 + r (r < RPT).  Threads are laid out [blockDim.y][blockDim.x], with
-// blockDim.x a multiple of 64 and every thread of a row sharing rhs0.
-// part/nparts: this block's slot among the nparts blocks that cover one
-// right-hand side; total_blocks: blocks in the launch (all of them arrive at
-// the counter).
+// vals[r][c] are this thread's contributions for right-hand side rhs0 + r
+// (r < RPT); blockDim.x is a multiple of 64.  part/nparts: this block's slot
+// among the blocks that cover one right-hand side.
 template <int RPT, int NC>
-__device__ void block_reduce_finalize(const RedArgs& ra, double (&vals)[RPT][NC], int rhs0,
-                                      int nrhs, int part, int nparts, int total_blocks) {
+__device__ void block_reduce_store(const RedArgs& ra, double (&vals)[RPT][NC], int rhs0, int nrhs, int part,
+                                   int nparts) {
   __shared__ double red[16][RPT * NC];
-  __shared__ int is_last;
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int waves_per_row = blockDim.x >> 6;
+  const int nwaves = blockDim.x >> 6;
 #pragma unroll
   for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -597,51 +641,15 @@ __device__ void block_reduce_finalize(const RedArgs& ra, double (&vals)[RPT][NC]
       if (lane == 0) red[wave][r * NC + c] = s;
     }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int r = 0; r < RPT; ++r) {
-      int rhs = rhs0 + r;
-      if (rhs >= nrhs) continue;
-      for (int c = 0; c < NC; ++c) {
-        double s = 0.0;
-        for (int w = 0; w < waves_per_row; ++w) s += red[threadIdx.y * waves_per_row + w][r * NC + c];
-        ra.partials[((size_t)rhs * nparts + part) * NC + c] = s;
-      }
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    unsigned prev = atomicAdd(ra.counter, 1u);
-    is_last = (prev == (unsigned)(total_blocks - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  // Last block: fixed-order sum per (rhs, c) with the block's threads.
-  __shared__ double tree[256];
-  const int nthr = blockDim.x * blockDim.y;
-  for (int rhs = 0; rhs < nrhs; ++rhs) {
-    double tot[NC];
-    for (int c = 0; c < NC; ++c) {
+  if (tid < RPT * NC) {
+    const int r = tid / NC, c = tid % NC;
+    const int rhs = rhs0 + r;
+    if (rhs < nrhs) {
       double s = 0.0;
-      if (tid < 256) {
-        for (int b = tid; b < nparts; b += (nthr < 256 ? nthr : 256))
-          s += __hip_atomic_load(&ra.partials[((size_t)rhs * nparts + b) * NC + c], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-        tree[tid] = s;
-      }
-      __syncthreads();
-      const int n = nthr < 256 ? nthr : 256;
-      for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w && tid + w < n) tree[tid] += tree[tid + w];
-        __syncthreads();
-      }
-      tot[c] = tree[0];
-      __syncthreads();
+      for (int w = 0; w < nwaves; ++w) s += red[w][r * NC + c];
+      ra.partials[((size_t)rhs * nparts + part) * NC + c] = s;
     }
-    if (tid == 0) cg_finalize(ra.state[rhs], ra.kind, tot[0], NC > 1 ? tot[NC - 1] : 0.0);
   }
-  if (tid == 0) *ra.counter = 0u;
 }
 
 }  // namespace dirac

@@ -24,6 +24,10 @@
 namespace dirac {
 
 enum Epi : int { kEpiStore = 0, kEpiStoreNorm = 1, kEpiSubNorm = 2 };
+
+// Second reduction stage (field.hip): sums partials[rhs][nparts][nc] per
+// right-hand side in a fixed order and applies cg_finalize.
+hipError_t launch_finalize(const RedArgs& ra, int nparts, int nrhs, int nc, hipStream_t st);
 enum Gate : int { kGateNone = 0, kGateNotDone = 1, kGateActive = 2 };
 
 struct DslashArgs {
@@ -45,6 +49,8 @@ struct DslashArgs {
   int ngroups;       // ceil(nrhs / R)
   int sub_alpha;     // kEpiSubNorm: c = state.alpha (1) or 1 (0)
   int gate;          // Gate
+  int nt_store;      // non-temporal output stores (kEpiStore / kEpiStoreNorm)
+  int sy, sz, tc;    // streaming kernel: tile rows in y, planes in z, t slices per block
   RedArgs red;
 };
 
@@ -151,7 +157,11 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int p, int i, i
     Cx<Ro> o[12];
     convert12(acc[r], o);
     if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
-      SO::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, o);
+      const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
+      if (a.nt_store)
+        SO::template store<2>(orsrc, Vh, p, i, o);
+      else
+        SO::template store<0>(orsrc, Vh, p, i, o);
       if constexpr (EPI == kEpiStoreNorm) {
         // <p, D^dag t_stored> = Re <D p, t_stored>: pair the exact result with
         // the value as stored, so that the CG step matches the vector the
@@ -222,8 +232,143 @@ k_dslash(DslashArgs a) {
   for (int r = 0; r < R; ++r) vals[r][0] = 0.0;
   if (any) dslash_site<PI, PO, LK, DAG, EPI, R>(a, p, i, rhs0, on, vals);
   if constexpr (EPI != kEpiStore) {
-    block_reduce_finalize<R, 1>(a.red, vals, rhs0, a.nrhs, tile, a.ntiles, nblocks);
+    block_reduce_store<R, 1>(a.red, vals, rhs0, a.nrhs, tile, a.ntiles);
   }
+}
+
+// Direction-split variant for lattices too small to fill the device with one
+// thread per site: NS waves share a block of 64 sites, wave w applies the
+// hops of directions {w} (NS = 4) or {2w, 2w+1} (NS = 2) to all 64 sites,
+// the NS partial spinors meet in LDS, and each wave finishes (mass term,
+// epilogue, store) its share of the output storage vectors.  NS times more
+// waves are in flight for the same lattice, each with a shorter dependency
+// chain.  One right-hand side.
+template <int PI, int PO, int LK, bool DAG, int EPI, int NS>
+__global__ void __launch_bounds__(64 * NS) __attribute__((amdgpu_waves_per_eu(dslash_waves<PI, 1>())))
+k_dslash_split(DslashArgs a) {
+  using SI = SpinFmt<PI>;
+  using SO = SpinFmt<PO>;
+  using Rl = typename SI::R;
+  using Ro = typename SO::R;
+  __shared__ Rl part[NS][24][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int Vh = a.g.Vh;
+  const int tile = xcd_tile(blockIdx.x, a.ntiles, a.remap);
+  const int p = tile & 1;
+  const int i = (tile >> 1) * 64 + lane;
+  bool on = i < Vh;
+  if (on && a.gate == kGateNotDone) on = !a.red.state[0].done;
+  if (on && a.gate == kGateActive) on = a.red.state[0].active != 0;
+  Cx<Rl> acc[1][12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[0][k] = {Rl(0), Rl(0)};
+  const Rsrc in[1] = {make_rsrc(a.in, a.field_bytes)};
+  if (on) {
+    const bool onr[1] = {true};
+    const Coord c = cb_coords(a.g, p, i);
+    const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
+    if constexpr (NS == 4) {
+      if (wave == 0) hop_dir<PI, LK, DAG, 1, 0>(a, Ur, in, c, p, i, onr, acc);
+      else if (wave == 1) hop_dir<PI, LK, DAG, 1, 1>(a, Ur, in, c, p, i, onr, acc);
+      else if (wave == 2) hop_dir<PI, LK, DAG, 1, 2>(a, Ur, in, c, p, i, onr, acc);
+      else hop_dir<PI, LK, DAG, 1, 3>(a, Ur, in, c, p, i, onr, acc);
+    } else {
+      if (wave == 0) {
+        hop_dir<PI, LK, DAG, 1, 0>(a, Ur, in, c, p, i, onr, acc);
+        hop_dir<PI, LK, DAG, 1, 1>(a, Ur, in, c, p, i, onr, acc);
+      } else {
+        hop_dir<PI, LK, DAG, 1, 2>(a, Ur, in, c, p, i, onr, acc);
+        hop_dir<PI, LK, DAG, 1, 3>(a, Ur, in, c, p, i, onr, acc);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    part[wave][2 * k][lane] = acc[0][k].re;
+    part[wave][2 * k + 1][lane] = acc[0][k].im;
+  }
+  __syncthreads();
+
+  // Output storage vectors [v0, v1) of this wave (scaled formats need the
+  // whole site for the scale: wave 0 takes all of them).
+  constexpr int NVO = SO::NV;
+  constexpr int CPV = 12 / NVO;
+  const int v0 = SO::kScaled ? (wave == 0 ? 0 : NVO) : wave * NVO / NS;
+  const int v1 = SO::kScaled ? NVO : (wave + 1) * NVO / NS;
+  double vals[1][1] = {{0.0}};
+  if (on && v0 < v1) {
+    const int c0 = v0 * CPV, c1 = v1 * CPV;
+    Cx<Rl> ctr[12];
+    if constexpr (SI::kScaled || SpinFmt<PI>::NV != NVO)
+      SI::load(in[0], Vh, p, i, ctr);
+    else
+      SI::load_range(in[0], Vh, p, i, ctr, v0, v1);
+    const Rl m4 = (Rl)a.mass4;
+    Cx<Ro> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      o[k] = {Ro(0), Ro(0)};
+      if (k >= c0 && k < c1) {
+        Rl re = 0, im = 0;
+#pragma unroll
+        for (int d = 0; d < NS; ++d) {
+          re += part[d][2 * k][lane];
+          im += part[d][2 * k + 1][lane];
+        }
+        o[k] = {(Ro)fma(m4, ctr[k].re, Rl(0.5) * re), (Ro)fma(m4, ctr[k].im, Rl(0.5) * im)};
+      }
+    }
+    if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+      const Rsrc orsrc = make_rsrc(a.out, a.out_bytes);
+      if constexpr (SO::kScaled) {
+        if (a.nt_store)
+          SO::template store<2>(orsrc, Vh, p, i, o);
+        else
+          SO::template store<0>(orsrc, Vh, p, i, o);
+      } else {
+        if (a.nt_store)
+          SO::template store_range<2>(orsrc, Vh, p, i, o, v0, v1);
+        else
+          SO::template store_range<0>(orsrc, Vh, p, i, o, v0, v1);
+      }
+      if constexpr (EPI == kEpiStoreNorm) {
+        Cx<Ro> q[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = o[k];
+        SO::round(q);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+        vals[0][0] = s;
+      }
+    } else {
+      static_assert(!SO::kScaled, "subtraction epilogue writes float32/float64");
+      const Ro cf = a.sub_alpha ? (Ro)a.red.state[0].alpha : Ro(1);
+      const Rsrc sr = make_rsrc(a.src, a.out_bytes);
+      Cx<Ro> dd[12];
+      SO::load_range(sr, Vh, p, i, dd, v0, v1);
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        dd[k].re = fma(-cf, o[k].re, dd[k].re);
+        dd[k].im = fma(-cf, o[k].im, dd[k].im);
+        s += (double)dd[k].re * dd[k].re + (double)dd[k].im * dd[k].im;
+      }
+      SO::template store_range<0>(make_rsrc(a.out, a.out_bytes), Vh, p, i, dd, v0, v1);
+      vals[0][0] = s;
+    }
+  }
+  if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, 0, 1, tile, a.ntiles);
+}
+
+template <int PI, int PO, int LK, bool DAG, int EPI, int NS>
+hipError_t launch_dslash_split(DslashArgs a, hipStream_t st) {
+  a.ngroups = 1;
+  a.ntiles = 2 * ((a.g.Vh + 63) / 64);
+  hipLaunchKernelGGL((k_dslash_split<PI, PO, LK, DAG, EPI, NS>), dim3(a.ntiles), dim3(64 * NS), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || EPI == kEpiStore) return e;
+  return launch_finalize(a.red, a.ntiles, 1, 1, st);
 }
 
 typedef hipError_t (*DslashLaunchFn)(DslashArgs, int block_sites, hipStream_t);
@@ -234,9 +379,18 @@ hipError_t launch_dslash(DslashArgs a, int S, hipStream_t st) {
   a.ntiles = 2 * ((a.g.Vh + S - 1) / S);
   const int nblocks = a.ntiles * a.ngroups;
   hipLaunchKernelGGL((k_dslash<PI, PO, LK, DAG, EPI, R>), dim3(nblocks), dim3(S), 0, st, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || EPI == kEpiStore) return e;
+  return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);
 }
 
+template <int PI, int PO, int LK, bool DAG, int EPI, int NS>
+hipError_t launch_split_entry(DslashArgs a, int, hipStream_t st) {
+  return launch_dslash_split<PI, PO, LK, DAG, EPI, NS>(a, st);
+}
+
+// rpt > 0: one-thread-per-site kernel with rpt right-hand sides per thread;
+// rpt = -NS: direction-split kernel with NS waves per block of 64 sites.
 struct DslashEntry {
   int pin, pout, link, dag, epi, rpt;
   DslashLaunchFn fn;
@@ -244,5 +398,7 @@ struct DslashEntry {
 
 #define DIRAC_DSLASH_ENTRY(PI, PO, LK, DAG, EPI, R) \
   DslashEntry{PI, PO, LK, DAG, EPI, R, &launch_dslash<PI, PO, LK, DAG, EPI, R>}
+#define DIRAC_DSLASH_SPLIT_ENTRY(PI, PO, LK, DAG, EPI, NS) \
+  DslashEntry{PI, PO, LK, DAG, EPI, -NS, &launch_split_entry<PI, PO, LK, DAG, EPI, NS>}
 
 }  // namespace dirac

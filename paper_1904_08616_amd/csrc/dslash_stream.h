@@ -1,0 +1,308 @@
+// t-streaming variant of the eq. (1) stencil with LDS staging.
+//
+// A block owns a tile of (x, y, z) columns -- all of x, tile_y rows of y,
+// tile_z planes of z -- one thread per column, and walks t_chunk consecutive
+// time slices.  At each slice the block's spinors psi(t) sit in LDS, so the
+// x, y and z neighbours of a site are read from LDS (only the y and z faces
+// of the tile reach to global memory); the t neighbours never leave the
+// thread: psi(t+1) is loaded one slice ahead and becomes the next slice's
+// centre, and the backward-t hop U_t(n)^dag (1 +- gamma_t) psi(n) is formed
+// while U_t(n) and psi(n) are in registers and carried to site n + t.
+// Every spinor is therefore read from memory about once per sweep instead
+// of up to nine times, and every U_t once instead of twice; the U_x, U_y,
+// U_z of a site are read by its own thread and again (backward hop) by the
+// neighbour thread a few instructions later, which the caches serve.
+#pragma once
+
+#include "dslash_impl.h"
+
+namespace dirac {
+
+// [12 components][NC columns] complex; NC is a compile-time constant so
+// that the component stride is an immediate offset of the LDS instruction.
+template <int PI, int NC>
+struct StreamLds {
+  using R = typename SpinFmt<PI>::R;
+  Cx<R>* base;
+  __device__ __forceinline__ void put(int col, const Cx<R> (&v)[12]) const {
+    Cx<R>* b = base + col;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) b[k * NC] = v[k];
+  }
+  __device__ __forceinline__ void get(int col, Cx<R> (&v)[12]) const {
+    const Cx<R>* b = base + col;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = b[k * NC];
+  }
+};
+
+// Complete the accumulation up to this point and keep the scheduler from
+// moving loads of later hops above it (bounds the registers in flight).
+template <class R>
+__device__ __forceinline__ void pin12(Cx<R> (&acc)[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Lexicographic parity and checkerboard index of (x, y, z, t).
+__device__ __forceinline__ void site_pi(const Geom& g, int x, int y, int z, int t, int& p, int& i) {
+  p = (x + y + z + t) & 1;
+  i = (((t * g.Z + z) * g.Y + y) * g.X + x) >> 1;
+}
+
+// One hop of eq. (1) from an already loaded neighbour spinor v:
+// FWD: acc += U (1 - S gamma_mu) v;  backward: acc += U^dag (1 + S gamma_mu) v.
+template <int MU, bool DAG, bool FWD, class R>
+__device__ __forceinline__ void hop_apply(const M3<R>& u, const Cx<R> (&v)[12], Cx<R> (&acc)[12]) {
+  constexpr int S = DAG ? -1 : 1;
+  Cx<R> h[2][3], w[2][3];
+  if constexpr (FWD) {
+    project<MU, -S>(v, h);
+    su3_mul(u, h, w);
+    reconstruct_add<MU, -S>(acc, w);
+  } else {
+    project<MU, S>(v, h);
+    su3_dag_mul(u, h, w);
+    reconstruct_add<MU, S>(acc, w);
+  }
+}
+
+#ifndef DIRAC_STREAM_WAVES_F32
+#define DIRAC_STREAM_WAVES_F32 3
+#endif
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC>
+__global__ void __launch_bounds__(NC)
+__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? 2 : DIRAC_STREAM_WAVES_F32)))
+k_dslash_stream(DslashArgs a) {
+  using SI = SpinFmt<PI>;
+  using SO = SpinFmt<PO>;
+  using LF = LinkFmt<PI, LK>;
+  using Rl = typename SI::R;
+  using Ro = typename SO::R;
+  constexpr int S = DAG ? -1 : 1;
+  extern __shared__ __align__(16) char lds_raw[];
+  const Geom g = a.g;
+  const int Vh = g.Vh;
+  const int BY = a.sy, BZ = a.sz;
+  const StreamLds<PI, NC> lds{reinterpret_cast<Cx<Rl>*>(lds_raw)};
+
+  const int tid = threadIdx.x;
+  const int x = tid % g.X;
+  const int yl = (tid / g.X) % BY;
+  const int zl = tid / (g.X * BY);
+  const int nty = g.Y / BY, ntz = g.Z / BZ;
+  const int nblocks = a.ntiles;
+  const int l = xcd_tile(blockIdx.x, nblocks, a.remap);
+  const int ty = l % nty;
+  const int tz = (l / nty) % ntz;
+  const int tt = l / (nty * ntz);
+  const int y = ty * BY + yl, z = tz * BZ + zl;
+  const int t0 = tt * a.tc;
+  const int t1 = min(t0 + a.tc, g.T);
+
+  bool on = true;
+  if (a.gate == kGateNotDone) on = !a.red.state[0].done;
+  if (a.gate == kGateActive) on = a.red.state[0].active != 0;
+  double vals[1][1] = {{0.0}};
+  if (on) {
+    const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
+    const Rsrc in = make_rsrc(a.in, a.field_bytes);
+    const int xp = (x + 1 == g.X) ? 0 : x + 1, xm = (x == 0) ? g.X - 1 : x - 1;
+    const int yp = (y + 1 == g.Y) ? 0 : y + 1, ym = (y == 0) ? g.Y - 1 : y - 1;
+    const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
+    const int col_xp = tid - x + xp, col_xm = tid - x + xm;
+    const bool in_yp = yl + 1 < BY, in_ym = yl > 0, in_zp = zl + 1 < BZ, in_zm = zl > 0;
+
+    // prologue: centre psi(t0) and the backward-t hop carried into t0.  The
+    // carried hop is kept as its half spinor w = U^dag h (12 reals); the
+    // centre lives in LDS during a slice and is read back at its end.
+    Cx<Rl> nxt[12];
+    Cx<Rl> Wt[2][3];
+    // float64: the carried half spinor waits in a private LDS slot (registers
+    // are the scarce resource at two waves per SIMD)
+    Cx<Rl>* wslot = reinterpret_cast<Cx<Rl>*>(lds_raw) + 12 * NC + tid;
+    constexpr bool kWtInLds = (PI == DIRAC_F64);
+    {
+      int p, i;
+      site_pi(g, x, y, z, t0, p, i);
+      SI::load(in, Vh, p, i, nxt);
+      const int tm = (t0 == 0) ? g.T - 1 : t0 - 1;
+      int pm, im;
+      site_pi(g, x, y, z, tm, pm, im);
+      Cx<Rl> v[12];
+      SI::load(in, Vh, pm, im, v);
+      M3<Rl> u;
+      LF::load(Ur, Vh, pm, 3, im, u);
+      Cx<Rl> h[2][3];
+      project<3, S>(v, h);
+      su3_dag_mul(u, h, Wt);
+      if constexpr (kWtInLds) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
+      }
+    }
+
+#pragma nounroll
+    for (int t = t0; t < t1; ++t) {
+      int p, i;
+      site_pi(g, x, y, z, t, p, i);
+      lds.put(tid, nxt);  // this slice's centre
+      const int tn = (t + 1 == g.T) ? 0 : t + 1;
+      {
+        int pn, in_;
+        site_pi(g, x, y, z, tn, pn, in_);
+        SI::load(in, Vh, pn, in_, nxt);
+      }
+      __syncthreads();
+
+      Cx<Rl> acc[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[k] = {Rl(0), Rl(0)};
+      if constexpr (kWtInLds) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Wt[k / 3][k % 3] = wslot[k * NC];
+      }
+      reconstruct_add<3, S>(acc, Wt);  // backward t hop
+      Cx<Rl> cur[12];
+      {
+        M3<Rl> u;
+        Cx<Rl> v[12];
+        // x: both neighbours are in the tile (it spans all of x)
+        LF::load(Ur, Vh, p, 0, i, u);
+        lds.get(col_xp, v);
+        hop_apply<0, DAG, true>(u, v, acc);
+        {
+          int pb, ib;
+          site_pi(g, xm, y, z, t, pb, ib);
+          LF::load(Ur, Vh, pb, 0, ib, u);
+        }
+        lds.get(col_xm, v);
+        hop_apply<0, DAG, false>(u, v, acc);
+        pin12(acc);
+        // y
+        LF::load(Ur, Vh, p, 1, i, u);
+        if (in_yp) {
+          lds.get(tid + g.X, v);
+        } else {
+          int pf, jf;
+          site_pi(g, x, yp, z, t, pf, jf);
+          SI::load(in, Vh, pf, jf, v);
+        }
+        hop_apply<1, DAG, true>(u, v, acc);
+        {
+          int pb, ib;
+          site_pi(g, x, ym, z, t, pb, ib);
+          LF::load(Ur, Vh, pb, 1, ib, u);
+          if (in_ym)
+            lds.get(tid - g.X, v);
+          else
+            SI::load(in, Vh, pb, ib, v);
+        }
+        hop_apply<1, DAG, false>(u, v, acc);
+        pin12(acc);
+        // z
+        LF::load(Ur, Vh, p, 2, i, u);
+        if (in_zp) {
+          lds.get(tid + g.X * BY, v);
+        } else {
+          int pf, jf;
+          site_pi(g, x, y, zp, t, pf, jf);
+          SI::load(in, Vh, pf, jf, v);
+        }
+        hop_apply<2, DAG, true>(u, v, acc);
+        {
+          int pb, ib;
+          site_pi(g, x, y, zm, t, pb, ib);
+          LF::load(Ur, Vh, pb, 2, ib, u);
+          if (in_zm)
+            lds.get(tid - g.X * BY, v);
+          else
+            SI::load(in, Vh, pb, ib, v);
+        }
+        hop_apply<2, DAG, false>(u, v, acc);
+        pin12(acc);
+        // t: forward hop with psi(t+1); the backward hop for t+1 from U_t(n), psi(n)
+        LF::load(Ur, Vh, p, 3, i, u);
+        hop_apply<3, DAG, true>(u, nxt, acc);
+        lds.get(tid, cur);
+        Cx<Rl> h[2][3];
+        project<3, S>(cur, h);
+        su3_dag_mul(u, h, Wt);
+        if constexpr (kWtInLds) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
+        }
+      }
+
+      // epilogue at site (p, i) with centre cur
+      const Rl m4 = (Rl)a.mass4;
+      Cx<Ro> o[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
+      const Rsrc orsrc = make_rsrc(a.out, a.out_bytes);
+      if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+        if (a.nt_store)
+          SO::template store<2>(orsrc, Vh, p, i, o);
+        else
+          SO::template store<0>(orsrc, Vh, p, i, o);
+        if constexpr (EPI == kEpiStoreNorm) {
+          Cx<Ro> q[12];
+#pragma unroll
+          for (int k = 0; k < 12; ++k) q[k] = o[k];
+          SO::round(q);
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+          vals[0][0] += s;
+        }
+      } else {
+        const Ro cf = a.sub_alpha ? (Ro)a.red.state[0].alpha : Ro(1);
+        Cx<Ro> d[12];
+        SO::load(make_rsrc(a.src, a.out_bytes), Vh, p, i, d);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          d[k].re = fma(-cf, o[k].re, d[k].re);
+          d[k].im = fma(-cf, o[k].im, d[k].im);
+          s += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+        }
+        SO::template store<0>(orsrc, Vh, p, i, d);
+        vals[0][0] += s;
+      }
+      __syncthreads();  // every read of this slice's LDS is done
+    }
+  }
+  if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, 0, 1, blockIdx.x, nblocks);
+}
+
+// Tile/geometry check of the streaming kernel (host).
+inline bool stream_fits(const Geom& g, int sy, int sz, int tc) {
+  if (sy < 1 || sz < 1 || tc < 1) return false;
+  if (g.Y % sy || g.Z % sz) return false;
+  const int n = g.X * sy * sz;
+  return n == 128 || n == 256;
+}
+
+template <int PI, int PO, int LK, bool DAG, int EPI>
+hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
+  if (!stream_fits(a.g, a.sy, a.sz, a.tc) || a.nrhs != 1) return hipErrorInvalidValue;
+  const int nty = a.g.Y / a.sy, ntz = a.g.Z / a.sz, ntt = (a.g.T + a.tc - 1) / a.tc;
+  a.ntiles = nty * ntz * ntt;
+  a.ngroups = 1;
+  const int ncols = a.g.X * a.sy * a.sz;
+  const size_t lds = (size_t)ncols * (PI == DIRAC_F64 ? 18 : 12) * sizeof(Cx<typename SpinFmt<PI>::R>);
+  if (ncols == 256)
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), dim3(a.ntiles), dim3(256), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128>), dim3(a.ntiles), dim3(128), lds, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || EPI == kEpiStore) return e;
+  return launch_finalize(a.red, a.ntiles, 1, 1, st);
+}
+
+#define DIRAC_DSLASH_STREAM_ENTRY(PI, PO, LK, DAG, EPI) \
+  DslashEntry{PI, PO, LK, DAG, EPI, 0, &launch_dslash_stream<PI, PO, LK, DAG, EPI>}
+
+}  // namespace dirac

@@ -14,11 +14,10 @@ struct FieldRef {
   uint32_t bytes;  // bytes of one field
 };
 
-// Reduction target of a launch: partial sums go to `partials`, the last block
-// applies `kind` to state[rhs] (see cg_finalize).
+// Reduction target of a launch: partial sums go to `partials`, and a second
+// one-block-per-RHS kernel applies `kind` to state[rhs] (see cg_finalize).
 struct RedTarget {
   double* partials;
-  unsigned* counter;
   CgState* state;
   int kind;
 };

@@ -135,10 +135,36 @@ __device__ __forceinline__ void site_reduce(const RedArgs& ra, double (&v)[NC], 
   double vals[1][NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) vals[0][c] = v[c];
-  block_reduce_finalize<1, NC>(ra, vals, blockIdx.y, nrhs, blockIdx.x, 2 * nb, 2 * nb * nrhs);
+  block_reduce_store<1, NC>(ra, vals, blockIdx.y, nrhs, blockIdx.x, 2 * nb);
 }
 
-RedArgs red_args(const RedTarget& t) { return RedArgs{t.partials, t.counter, t.state, t.kind}; }
+RedArgs red_args(const RedTarget& t) { return RedArgs{t.partials, t.state, t.kind}; }
+
+// One block per right-hand side: fixed-order sum of its partials.
+constexpr int kFinBlock = 1024;
+template <int NC>
+__global__ void __launch_bounds__(kFinBlock) k_finalize(RedArgs ra, int nparts) {
+  __shared__ double tree[kFinBlock][NC];
+  const int rhs = blockIdx.x;
+  const int tid = threadIdx.x;
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0.0;
+  const double* p = ra.partials + (size_t)rhs * nparts * NC;
+  for (int b = tid; b < nparts; b += kFinBlock)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] += p[(size_t)b * NC + c];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) tree[tid][c] = s[c];
+  __syncthreads();
+  for (int w = kFinBlock / 2; w > 0; w >>= 1) {
+    if (tid < w)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) tree[tid][c] += tree[tid + w][c];
+    __syncthreads();
+  }
+  if (tid == 0) cg_finalize(ra.state[rhs], ra.kind, tree[0][0], NC > 1 ? tree[0][NC - 1] : 0.0);
+}
 
 // dst = c * src, optional |dst|^2
 template <int PS, int PD, bool NORM>
@@ -342,6 +368,14 @@ __global__ void __launch_bounds__(kBlock) k_force(Geom g, int nb, const char* gi
     default: return hipErrorInvalidValue;                                    \
   }
 
+hipError_t launch_finalize(const RedArgs& ra, int nparts, int nrhs, int nc, hipStream_t st) {
+  if (nc == 1)
+    hipLaunchKernelGGL(k_finalize<1>, dim3(nrhs), dim3(kFinBlock), 0, st, ra, nparts);
+  else
+    hipLaunchKernelGGL(k_finalize<2>, dim3(nrhs), dim3(kFinBlock), 0, st, ra, nparts);
+  return hipGetLastError();
+}
+
 hipError_t pack_spinor(const Geom& g, int nrhs, const void* src, FieldRef dst, hipStream_t st) {
   SiteGrid sg = site_grid(g, nrhs);
   PREC_SWITCH(dst.prec, hipLaunchKernelGGL(k_pack_spinor<P_>, sg.grid, dim3(kBlock), 0, st, g, sg.nb,
@@ -381,10 +415,13 @@ template <int PS>
 static hipError_t convert_from(const Geom& g, int nrhs, FieldRef src, FieldRef dst, const CgState* cs,
                                int ci, const RedTarget* red, hipStream_t st) {
   SiteGrid sg = site_grid(g, nrhs);
-  RedArgs ra = red ? red_args(*red) : RedArgs{nullptr, nullptr, nullptr, 0};
+  RedArgs ra = red ? red_args(*red) : RedArgs{nullptr, nullptr, 0};
   if (red) {
     PREC_SWITCH(dst.prec, hipLaunchKernelGGL((k_convert<PS, P_, true>), sg.grid, dim3(kBlock), 0, st, g,
                                              sg.nb, nrhs, dev(src), dev(dst), cs, ci, ra));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize(ra, 2 * sg.nb, nrhs, 1, st);
   } else {
     PREC_SWITCH(dst.prec, hipLaunchKernelGGL((k_convert<PS, P_, false>), sg.grid, dim3(kBlock), 0, st, g,
                                              sg.nb, nrhs, dev(src), dev(dst), cs, ci, ra));
@@ -409,7 +446,9 @@ static hipError_t dot_from(const Geom& g, int nrhs, FieldRef a, FieldRef b, cons
   SiteGrid sg = site_grid(g, nrhs);
   PREC_SWITCH(b.prec, hipLaunchKernelGGL((k_dot<PA, P_>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, nrhs,
                                          dev(a), dev(b), red_args(red)));
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(red_args(red), 2 * sg.nb, nrhs, 2, st);
 }
 
 hipError_t dot(const Geom& g, int nrhs, FieldRef a, FieldRef b, const RedTarget& red, hipStream_t st) {
@@ -426,7 +465,9 @@ hipError_t norm2(const Geom& g, int nrhs, FieldRef a, const RedTarget& red, hipS
   SiteGrid sg = site_grid(g, nrhs);
   PREC_SWITCH(a.prec, hipLaunchKernelGGL((k_norm2<P_>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, nrhs,
                                          dev(a), red_args(red)));
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(red_args(red), 2 * sg.nb, nrhs, 1, st);
 }
 
 template <int PX>

@@ -10,6 +10,7 @@
 #include "dirac.h"
 #include "common.h"
 #include "dslash_impl.h"
+#include "dslash_stream.h"
 #include "field.h"
 
 namespace dirac {
@@ -37,10 +38,12 @@ FieldRef field_as(const OpInfo& o, int prec, const void* p);  // same geometry, 
 
 // Launch configuration of the Dslash kernels.
 struct LaunchCfg {
-  int S;      // threads (sites) per block
-  int R;      // right-hand sides per thread
+  int S;      // one-thread-per-site kernel: threads (sites) per block
+  int R;      // right-hand sides per thread (> 0) or direction split (-2, -4)
   int remap;  // XCD-aware tile order
-  int lds;    // LDS neighbour staging (not used by this kernel family: 0)
+  int lds;    // 1: t-streaming kernel with the current slice staged in LDS
+  int nt;     // non-temporal output stores
+  int sy, sz, tc;  // streaming kernel tile: y rows, z planes, t slices per block
   int tuned;
 };
 LaunchCfg launch_cfg(const OpInfo& o);
@@ -55,7 +58,6 @@ DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out
 // demand, one per device).
 struct Scratch {
   double* partials;
-  unsigned* counter;
   CgState* state;
 };
 int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out);

@@ -47,7 +47,7 @@ k_multi(MultiArgs m) {
     const int p = tile & 1;
     const int i = (tile >> 1) * kMultiBlock + threadIdx.x;
     if (i >= lt.g.Vh) continue;
-    DslashArgs a;
+    DslashArgs a{};  // every field defined (reading an undefined one is UB)
     a.g = lt.g;
     a.U = lt.U;
     a.U_bytes = lt.U_bytes;
@@ -61,6 +61,8 @@ k_multi(MultiArgs m) {
     a.src_stride = 0;
     a.mass4 = lt.mass4;
     a.nrhs = 1;
+    a.gate = kGateNone;
+    a.nt_store = 0;
     bool on[1] = {true};
     double vals[1][1] = {{0.0}};
     dslash_site<P, P, LK, DAG, kEpiStore, 1>(a, p, i, 0, on, vals);

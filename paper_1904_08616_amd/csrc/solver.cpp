@@ -38,7 +38,7 @@ namespace dirac {
 namespace {
 
 struct Layout {
-  int64_t state, counter, partials, r, p, t, r0, psi, plo, tlo, total;
+  int64_t state, partials, r, p, t, r0, psi, plo, tlo, total;
   int64_t nparts;  // partial slots per right-hand side
 };
 
@@ -53,7 +53,6 @@ Layout layout(const OpInfo& hi, int inner_prec) {
   const int nrhs = hi.nrhs;
   L.nparts = 2 * ((hi.g.Vh + 63) / 64);
   L.state = take(sizeof(CgState) * kMaxRhs);
-  L.counter = take(256);
   L.partials = take(L.nparts * nrhs * 2 * (int64_t)sizeof(double));
   const int64_t f64 = nrhs * align256(spinor_field_bytes(DIRAC_F64, hi.V));
   L.r = take(f64);
@@ -83,7 +82,7 @@ struct Ctx {
   CgState* dstate;
   std::vector<CgState> hstate;
   RedTarget red(int kind) const {
-    return RedTarget{(double*)(work + L.partials), (unsigned*)(work + L.counter), dstate, kind};
+    return RedTarget{(double*)(work + L.partials), dstate, kind};
   }
   FieldRef f(int64_t off, int prec) const { return field_as(hi, prec, work + off); }
   int pull() {
@@ -100,7 +99,7 @@ struct Ctx {
   }
 };
 
-RedArgs to_args(const RedTarget& t) { return RedArgs{t.partials, t.counter, t.state, t.kind}; }
+RedArgs to_args(const RedTarget& t) { return RedArgs{t.partials, t.state, t.kind}; }
 
 // sqrt of a reduced norm^2; NaN stays NaN (std::max would turn it into 0).
 double norm_of(double v) { return std::isnan(v) ? v : std::sqrt(v > 0.0 ? v : 0.0); }
@@ -461,8 +460,6 @@ int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const vo
   c.dstate = (CgState*)(c.work + L.state);
   c.hstate.assign(kMaxRhs, CgState{});
   std::memset(c.hstate.data(), 0, sizeof(CgState) * kMaxRhs);
-  rc = hip_status(hipMemsetAsync(c.work + L.counter, 0, 256, c.st), "clear counter");
-  if (rc != DIRAC_OK) return rc;
   rc = c.push();
   if (rc != DIRAC_OK) return rc;
 

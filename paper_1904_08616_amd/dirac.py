@@ -159,13 +159,14 @@ class Operator:
         return self.launch_config()
 
     def launch_config(self):
-        v = [C.c_int32() for _ in range(5)]
-        abi.check(self.lib.dirac_launch_config(C.byref(self.op), *[C.byref(x) for x in v]))
-        return dict(zip(("block_sites", "rhs_per_thread", "xcd_remap", "lds", "tuned"), [x.value for x in v]))
+        out = abi.DiracLaunch()
+        abi.check(self.lib.dirac_launch_config(C.byref(self.op), C.byref(out)))
+        return out.as_dict()
 
-    def set_launch_config(self, block_sites, rhs_per_thread=1, xcd_remap=1, lds=0):
-        abi.check(self.lib.dirac_set_launch_config(C.byref(self.op), block_sites, rhs_per_thread, xcd_remap,
-                                                   lds))
+    def set_launch_config(self, block_sites=128, rhs_per_thread=1, xcd_remap=1, lds=0, nt_store=0,
+                          tile_y=1, tile_z=1, t_chunk=1):
+        cfg = abi.DiracLaunch(block_sites, rhs_per_thread, xcd_remap, nt_store, lds, tile_y, tile_z, t_chunk, 0)
+        abi.check(self.lib.dirac_set_launch_config(C.byref(self.op), C.byref(cfg)))
 
 
 # -------------------------------------------------------------------- CG ----

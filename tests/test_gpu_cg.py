@@ -160,3 +160,17 @@ def test_failure_paths_and_resume():
     # zero source: x = 0 immediately
     x4, st4 = solve(U, np.zeros_like(eta), m)
     assert st4[0]["status"] == abi.OK and np.all(x4 == 0)
+
+
+@pytest.mark.parametrize("inner,R", [("f64", -4), ("f64", -2), ("f32", -4), ("f16s", -2)])
+def test_cg_with_split_kernels(inner, R):
+    # force the direction-split Dslash (its norm and residual-update
+    # epilogues) for every operator the solve uses
+    dims = (8, 4, 6, 8)
+    U, eta = inputs(dims, "exp", seed=9)
+    m = 0.1
+    for prec, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
+        D.Operator(dims, m, prec, link).set_launch_config(64, R, 1, 0, 0)
+    x, st = solve(U, eta, m, link=12, inner=inner)
+    assert st[0]["status"] == abi.OK
+    assert true_res(U, eta, x, m) < 1e-10

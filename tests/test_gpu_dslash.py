@@ -87,13 +87,14 @@ def test_launch_configs_agree_bitwise_and_with_oracle():
         first = None
         for S in (64, 128, 256):
             for remap in (0, 1):
-                op.set_launch_config(S, R, remap)
-                got = host(op.unpack_spinor(op.apply(Ui, pi)))
-                assert rel_inf(got, ref) <= 1e-13, (S, remap, R)
-                if first is None:
-                    first = got
-                else:
-                    assert np.array_equal(got, first), (S, remap, R)
+                for nt in (0, 1):
+                    op.set_launch_config(S, R, remap, 0, nt)
+                    got = host(op.unpack_spinor(op.apply(Ui, pi)))
+                    assert rel_inf(got, ref) <= 1e-13, (S, remap, R, nt)
+                    if first is None:
+                        first = got
+                    else:
+                        assert np.array_equal(got, first), (S, remap, R, nt)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16s"])
@@ -159,3 +160,27 @@ def test_full_size_32x32x32x64_sampled():
         print(f"32^3x64 {prec}/{link}: sampled err {err:.2e}")
         assert err <= tol
         del out
+
+
+@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
+                                           ("f16s", 12, 1.5e-3), ("bf16s", 12, 1.2e-2)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_split_kernel_parity(prec, link, tol, dagger):
+    # direction-split variants (2 or 4 waves per 64-site block) against the
+    # oracle on the rounded inputs, and against the one-thread-per-site kernel
+    dims = (6, 4, 10, 4)
+    U, psi = inputs(dims, "exp", seed=8)
+    m = 0.07
+    op = D.Operator(dims, m, prec, link)
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    f = wilson.dslash_dagger if dagger else wilson.dslash
+    ref = f(lowprec.store_links(U, prec), lowprec.store(psi, prec), m)
+    op.set_launch_config(128, 1, 1, 0, 0)
+    base = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
+    for R in (-2, -4):
+        for nt in (0, 1):
+            op.set_launch_config(64, R, 1, 0, nt)
+            got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
+            assert rel_inf(got, ref) <= tol, (R, nt)
+            assert rel_inf(got, base) <= (1e-14 if prec == "f64" else 2 * tol), (R, nt)
