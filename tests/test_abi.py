@@ -121,10 +121,13 @@ def test_launch_config_validation():
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(128, 5, 1, 0, 0, 1, 1, 1, 0))) == abi.EINVAL
     # streaming tiles must divide the lattice and have 128 or 256 columns
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 3, 1, 1, 0))) == abi.EINVAL
-    assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
-    assert lib.dirac_set_launch_config(C.byref(_op(nrhs=2)), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    op8 = _op(dims=(8, 4, 4, 4))
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
+    assert lib.dirac_set_launch_config(C.byref(_op(dims=(8, 4, 4, 4), nrhs=2)),
+                                       C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
     got = abi.DiracLaunch()
-    assert lib.dirac_launch_config(C.byref(op), C.byref(got)) == abi.OK
+    assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
     assert (got.lds, got.tile_y, got.tile_z, got.t_chunk, got.tuned) == (1, 4, 4, 2, 1)
     assert lib.dirac_multi_apply(0, None, None, None, None, 0, None) == abi.EINVAL
     assert lib.dirac_multi_apply(9, None, None, None, None, 0, None) == abi.EINVAL
