@@ -194,11 +194,18 @@ __device__ __forceinline__ T bld(Rsrc r, uint32_t voff, uint32_t soff) {
 }
 // AUX = 0: ordinary store; AUX = 2: non-temporal (streaming) store that does
 // not keep the line in the L2.
+//
+// A 128-bit store never takes its offset in an SGPR (soffset): a VALU write
+// to the store's data registers right after such a store needs a wait state,
+// and the compiler only inserts it when soffset is the constant 0.  Without
+// it the store can pick up the new register value under load (seen as
+// sporadically corrupted first dwords).  The plane offset is therefore added
+// to the per-lane offset, which costs one VALU add per store.
 template <int AUX = 0, class T>
 __device__ __forceinline__ void bst(Rsrc r, uint32_t voff, uint32_t soff, const T& v) {
   static_assert(sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4, "buffer store size");
   if constexpr (sizeof(T) == 16) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, AUX);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff + soff, 0, AUX);
   } else if constexpr (sizeof(T) == 8) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, AUX);
   } else {

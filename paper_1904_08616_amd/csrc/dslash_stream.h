@@ -85,7 +85,6 @@ k_dslash_stream(DslashArgs a) {
   const Geom g = a.g;
   const int Vh = g.Vh;
   const int BY = a.sy, BZ = a.sz;
-  const StreamLds<PI, NC> lds{reinterpret_cast<Cx<Rl>*>(lds_raw)};
 
   const int tid = threadIdx.x;
   const int x = tid % g.X;
@@ -113,24 +112,24 @@ k_dslash_stream(DslashArgs a) {
     const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
     const int col_xp = tid - x + xp, col_xm = tid - x + xm;
     const bool in_yp = yl + 1 < BY, in_ym = yl > 0, in_zp = zl + 1 < BZ, in_zm = zl > 0;
-
-    // prologue: centre psi(t0) and the backward-t hop carried into t0.  The
-    // carried hop is kept as its half spinor w = U^dag h (12 reals); the
-    // centre lives in LDS during a slice and is read back at its end.
-    Cx<Rl> nxt[12];
-    Cx<Rl> Wt[2][3];
-    // float64: the carried half spinor waits in a private LDS slot (registers
-    // are the scarce resource at two waves per SIMD)
-    Cx<Rl>* wslot = reinterpret_cast<Cx<Rl>*>(lds_raw) + 12 * NC + tid;
+    // LDS: two slice buffers [2][12][NC] (slice t is read while t+1 is
+    // written) and, in float64, a private slot per thread for the carried hop.
+    Cx<Rl>* const lbase = reinterpret_cast<Cx<Rl>*>(lds_raw);
+    Cx<Rl>* const wslot = lbase + 24 * NC + tid;
     constexpr bool kWtInLds = (PI == DIRAC_F64);
+
+    // prologue: centre psi(t0) into buffer 0 and the backward-t hop carried
+    // into t0, kept as its half spinor w = U^dag h (12 reals)
+    Cx<Rl> Wt[2][3];
     {
       int p, i;
       site_pi(g, x, y, z, t0, p, i);
-      SI::load(in, Vh, p, i, nxt);
+      Cx<Rl> v[12];
+      SI::load(in, Vh, p, i, v);
+      StreamLds<PI, NC>{lbase}.put(tid, v);
       const int tm = (t0 == 0) ? g.T - 1 : t0 - 1;
       int pm, im;
       site_pi(g, x, y, z, tm, pm, im);
-      Cx<Rl> v[12];
       SI::load(in, Vh, pm, im, v);
       M3<Rl> u;
       LF::load(Ur, Vh, pm, 3, im, u);
@@ -142,19 +141,22 @@ k_dslash_stream(DslashArgs a) {
         for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
       }
     }
+    __syncthreads();
 
 #pragma nounroll
     for (int t = t0; t < t1; ++t) {
+      const int b = (t - t0) & 1;
+      const StreamLds<PI, NC> cur_s{lbase + b * 12 * NC};       // slice t
+      const StreamLds<PI, NC> nxt_s{lbase + (b ^ 1) * 12 * NC}; // slice t+1
       int p, i;
       site_pi(g, x, y, z, t, p, i);
-      lds.put(tid, nxt);  // this slice's centre
       const int tn = (t + 1 == g.T) ? 0 : t + 1;
+      Cx<Rl> nxt[12];
       {
         int pn, in_;
         site_pi(g, x, y, z, tn, pn, in_);
         SI::load(in, Vh, pn, in_, nxt);
       }
-      __syncthreads();
 
       Cx<Rl> acc[12];
 #pragma unroll
@@ -164,26 +166,26 @@ k_dslash_stream(DslashArgs a) {
         for (int k = 0; k < 6; ++k) Wt[k / 3][k % 3] = wslot[k * NC];
       }
       reconstruct_add<3, S>(acc, Wt);  // backward t hop
-      Cx<Rl> cur[12];
       {
         M3<Rl> u;
         Cx<Rl> v[12];
         // x: both neighbours are in the tile (it spans all of x)
         LF::load(Ur, Vh, p, 0, i, u);
-        lds.get(col_xp, v);
+        cur_s.get(col_xp, v);
         hop_apply<0, DAG, true>(u, v, acc);
         {
           int pb, ib;
           site_pi(g, xm, y, z, t, pb, ib);
           LF::load(Ur, Vh, pb, 0, ib, u);
         }
-        lds.get(col_xm, v);
+        cur_s.get(col_xm, v);
         hop_apply<0, DAG, false>(u, v, acc);
+        nxt_s.put(tid, nxt);  // psi(t+1) waits in LDS for the t hop and the next slice
         pin12(acc);
         // y
         LF::load(Ur, Vh, p, 1, i, u);
         if (in_yp) {
-          lds.get(tid + g.X, v);
+          cur_s.get(tid + g.X, v);
         } else {
           int pf, jf;
           site_pi(g, x, yp, z, t, pf, jf);
@@ -195,7 +197,7 @@ k_dslash_stream(DslashArgs a) {
           site_pi(g, x, ym, z, t, pb, ib);
           LF::load(Ur, Vh, pb, 1, ib, u);
           if (in_ym)
-            lds.get(tid - g.X, v);
+            cur_s.get(tid - g.X, v);
           else
             SI::load(in, Vh, pb, ib, v);
         }
@@ -204,7 +206,7 @@ k_dslash_stream(DslashArgs a) {
         // z
         LF::load(Ur, Vh, p, 2, i, u);
         if (in_zp) {
-          lds.get(tid + g.X * BY, v);
+          cur_s.get(tid + g.X * BY, v);
         } else {
           int pf, jf;
           site_pi(g, x, y, zp, t, pf, jf);
@@ -216,7 +218,7 @@ k_dslash_stream(DslashArgs a) {
           site_pi(g, x, y, zm, t, pb, ib);
           LF::load(Ur, Vh, pb, 2, ib, u);
           if (in_zm)
-            lds.get(tid - g.X * BY, v);
+            cur_s.get(tid - g.X * BY, v);
           else
             SI::load(in, Vh, pb, ib, v);
         }
@@ -224,10 +226,11 @@ k_dslash_stream(DslashArgs a) {
         pin12(acc);
         // t: forward hop with psi(t+1); the backward hop for t+1 from U_t(n), psi(n)
         LF::load(Ur, Vh, p, 3, i, u);
-        hop_apply<3, DAG, true>(u, nxt, acc);
-        lds.get(tid, cur);
+        nxt_s.get(tid, v);
+        hop_apply<3, DAG, true>(u, v, acc);
+        cur_s.get(tid, v);
         Cx<Rl> h[2][3];
-        project<3, S>(cur, h);
+        project<3, S>(v, h);
         su3_dag_mul(u, h, Wt);
         if constexpr (kWtInLds) {
 #pragma unroll
@@ -235,7 +238,9 @@ k_dslash_stream(DslashArgs a) {
         }
       }
 
-      // epilogue at site (p, i) with centre cur
+      // epilogue at site (p, i) with centre psi(t)
+      Cx<Rl> cur[12];
+      cur_s.get(tid, cur);
       const Rl m4 = (Rl)a.mass4;
       Cx<Ro> o[12];
 #pragma unroll
@@ -271,7 +276,7 @@ k_dslash_stream(DslashArgs a) {
         SO::template store<0>(orsrc, Vh, p, i, d);
         vals[0][0] += s;
       }
-      __syncthreads();  // every read of this slice's LDS is done
+      __syncthreads();  // slice t+1 complete; slice t no longer read
     }
   }
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, 0, 1, blockIdx.x, nblocks);
@@ -292,7 +297,7 @@ hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
   a.ntiles = nty * ntz * ntt;
   a.ngroups = 1;
   const int ncols = a.g.X * a.sy * a.sz;
-  const size_t lds = (size_t)ncols * (PI == DIRAC_F64 ? 18 : 12) * sizeof(Cx<typename SpinFmt<PI>::R>);
+  const size_t lds = (size_t)ncols * (PI == DIRAC_F64 ? 30 : 24) * sizeof(Cx<typename SpinFmt<PI>::R>);
   if (ncols == 256)
     hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), dim3(a.ntiles), dim3(256), lds, st, a);
   else

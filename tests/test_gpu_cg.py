@@ -128,6 +128,28 @@ def test_mixed_vs_oracle_solution(inner):
     assert err <= freefield.condition_number(m) * (1e-10 + 1e-12)
 
 
+@pytest.mark.parametrize("inner", ["f32", "f16s", "bf16s"])
+def test_mixed_first_iterations_vs_oracle_large(inner):
+    # 16^3 x 18: more than 2^15 sites per parity and a grid of several
+    # hundred blocks.  Three inner iterations of Algorithm 1 are compared with
+    # the oracle's emulation of the same storage formats: the iterate and the
+    # true residual agree up to the rounding-order differences of the formats.
+    dims = (16, 16, 16, 18)
+    U, eta = inputs(dims, "exp", seed=0)
+    m = 0.05
+    k = 3
+    x, st = solve(U, eta, m, link=12, inner=inner, max_iter=k, allow_failure=True, check_every=1)
+    assert st[0]["status"] == abi.ENOCONV and st[0]["iters"] == k
+    xo, info = solvers.mixed_cg(U, eta, m, tol=1e-10, inner_fmt=inner, max_iter=k)
+    assert info["iters"] == k
+    err = rel_2(x, xo)
+    dres = abs(st[0]["true_rel_res"] - info["true_rel_res"]) / info["true_rel_res"]
+    print(f"{inner} after {k} inner iterations: |x - x_oracle| {err:.2e}, residual "
+          f"{st[0]['true_rel_res']:.6f} vs {info['true_rel_res']:.6f}")
+    assert err <= 2e-3
+    assert dres <= 1e-3
+
+
 @pytest.mark.parametrize("inner", ["f64", "f32"])
 def test_batched_rhs_match_single(inner):
     dims = (8, 4, 4, 8)
@@ -171,6 +193,19 @@ def test_cg_with_split_kernels(inner, R):
     m = 0.1
     for prec, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
         D.Operator(dims, m, prec, link).set_launch_config(64, R, 1, 0, 0)
+    x, st = solve(U, eta, m, link=12, inner=inner)
+    assert st[0]["status"] == abi.OK
+    assert true_res(U, eta, x, m) < 1e-10
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
+def test_cg_with_stream_kernels(inner):
+    # the t-streaming Dslash with its norm and residual-update epilogues
+    dims = (16, 8, 4, 8)
+    U, eta = inputs(dims, "exp", seed=11)
+    m = 0.1
+    for prec in ("f64", "f32", "f16s"):
+        D.Operator(dims, m, prec, 12).set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=3)
     x, st = solve(U, eta, m, link=12, inner=inner)
     assert st[0]["status"] == abi.OK
     assert true_res(U, eta, x, m) < 1e-10

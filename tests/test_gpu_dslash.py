@@ -184,3 +184,34 @@ def test_split_kernel_parity(prec, link, tol, dagger):
             got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
             assert rel_inf(got, ref) <= tol, (R, nt)
             assert rel_inf(got, base) <= (1e-14 if prec == "f64" else 2 * tol), (R, nt)
+
+
+STREAM_CASES = [
+    # dims, (tile_y, tile_z), t_chunk    (tile = all of x times tile_y times tile_z: 128 or 256 columns)
+    ((8, 4, 4, 8), (4, 4), 1),
+    ((8, 4, 4, 8), (4, 4), 3),     # ragged last chunk
+    ((16, 8, 8, 6), (4, 2), 4),    # faces in y and z
+    ((16, 8, 8, 6), (8, 1), 2),
+    ((16, 4, 8, 6), (2, 8), 6),    # one chunk covers all of t
+    ((32, 4, 4, 4), (2, 2), 2),
+    ((32, 4, 4, 4), (4, 2), 1),
+]
+
+
+@pytest.mark.parametrize("dims,tile,tc", STREAM_CASES)
+@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
+                                           ("f16s", 12, 1.5e-3)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
+    U, psi = inputs(dims, "exp", seed=10)
+    m = 0.09
+    op = D.Operator(dims, m, prec, link)
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    f = wilson.dslash_dagger if dagger else wilson.dslash
+    ref = f(lowprec.store_links(U, prec), lowprec.store(psi, prec), m)
+    for remap in (0, 1):
+        op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc, xcd_remap=remap)
+        assert op.launch_config()["lds"] == 1
+        got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
+        assert rel_inf(got, ref) <= tol, (remap,)
