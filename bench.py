@@ -48,6 +48,39 @@ def site_bytes(prec, link, nrhs=1):
     return link_b + 2 * spin_b * nrhs
 
 
+def kernel_name(prec, link, cfg, dims, dagger=False):
+    """Which Dslash kernel a launch configuration selects, as rocprofv3 names it
+    (template arguments: input/output precision, link reals, dagger, epilogue,
+    then rhs per thread, waves per site or threads per block)."""
+    P = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}[prec]
+    args = f"{P}, {P}, {link}, {'true' if dagger else 'false'}, 0"
+    if cfg["lds"]:
+        nc = dims[0] * cfg["tile_y"] * cfg["tile_z"]
+        return (f"k_dslash_stream<{args}, {nc}> (tile all-x * {cfg['tile_y']} * {cfg['tile_z']}, "
+                f"t_chunk {cfg['t_chunk']})")
+    if cfg["rhs_per_thread"] < 0:
+        return f"k_dslash_split<{args}, {-cfg['rhs_per_thread']}> ({cfg['block_sites']} sites/block)"
+    return f"k_dslash<{args}, {cfg['rhs_per_thread']}> ({cfg['block_sites']} sites/block)"
+
+
+def counter_traffic(kernel, launch):
+    """HBM bytes per launch of ``kernel`` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernel sources or the launch
+    configuration differ from those the counters were taken with."""
+    from paper_1904_08616_amd.profile_summary import kernel_sources_sha256
+    path = os.path.join(ROOT, "profiles", "dslash_f64_16x16x16x32_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    if rec.get("launch") != launch or kernel.split(" (")[0] not in rec["FETCH_SIZE"]["kernel"]:
+        return None
+    return rec["traffic_bytes"]
+
+
 def gen_inputs(dims, seed=0, eps=0.3, nrhs=None):
     import synth
     g = synth.rng(seed)
@@ -227,12 +260,16 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "kernel": "k_dslash<F64,F64,18,false,store,1>",
+            "kernel": kernel_name("f64", 18, cfg, dims),
             "algorithmic_bytes_per_launch": bytes_per,
             "avg_launch_ms": round(ms, 5),
             "gflops": round(FLOPS_PER_SITE * V / (ms * 1e-3) / 1e9, 1),
         },
     }
+    traffic = counter_traffic(line["roofline"]["kernel"], cfg)
+    if traffic is not None:
+        line["roofline"]["traffic"] = round(traffic)
+        line["roofline"]["traffic_over_algorithmic"] = round(traffic / bytes_per, 3)
     extra = {}
     if copy:
         extra["copy_ceiling"] = copy
