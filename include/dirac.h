@@ -228,8 +228,11 @@ int dirac_plan_destroy(void* plan);
  *     tile_z planes (128 or 256 columns) and walks t_chunk time slices; the
  *     current slice is staged in LDS and the t neighbours stay in registers
  *     (nrhs = 1; tile_y | Ly and tile_z | Lz).
- * xcd_remap orders tiles so that each XCD sweeps one contiguous region;
- * nt_store writes the output with non-temporal stores. */
+ * xcd_remap orders tiles so that each XCD sweeps one contiguous region
+ * (0 or 1).  For the t-streaming kernel it is a mask: bit 0 that XCD order,
+ * bit 1 t-chunks fastest in the block order, bit 2 odd t-chunks walk down in
+ * t, so that neighbouring chunks read their shared halo slice at the same
+ * time.  nt_store writes the output with non-temporal stores. */
 typedef struct dirac_launch {
   int32_t block_sites;
   int32_t rhs_per_thread;
@@ -245,7 +248,8 @@ typedef struct dirac_launch {
  * same (device, geometry, precision, links, nrhs).  chi_int is overwritten.
  * Synchronises the stream.  If the environment variable DIRAC_TUNE_CACHE
  * names a file, results are appended there and read back by later
- * processes. */
+ * processes.  With DIRAC_TUNE_VERBOSE set (not "0") every candidate's time
+ * is printed to stderr. */
 int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int,
                    void* stream);
 

@@ -594,8 +594,9 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
           if (R < 0 && S != 64) continue;  // the split kernel has fixed 64-site blocks
           cands.push_back(LaunchCfg{S, R, remap, 0, nt, 1, 1, 1, 1});
         }
+  // streaming kernel: XCD order, t-chunks fastest, alternating walk (bits 0..2)
   for (const LaunchCfg& c0 : stream_candidates(o))
-    for (int remap : {0, 1})
+    for (int remap = 0; remap < 8; ++remap)
       for (int nt : {0, 1}) {
         LaunchCfg c = c0;
         c.remap = remap;
@@ -604,6 +605,8 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
       }
   LaunchCfg best{};
   float best_ms = 1e30f;
+  const char* verbose_env = std::getenv("DIRAC_TUNE_VERBOSE");
+  const bool verbose = verbose_env != nullptr && *verbose_env && *verbose_env != '0';
   int rc = DIRAC_OK;
   for (const LaunchCfg& c : cands) {
     rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
@@ -615,6 +618,9 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
     if (rc != DIRAC_OK) break;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
+    if (verbose)
+      std::fprintf(stderr, "dirac_autotune %s: S %d R %d remap %d lds %d nt %d tile %d x %d t_chunk %d: %.4f ms\n",
+                   cfg_key(o).c_str(), c.S, c.R, c.remap, c.lds, c.nt, c.sy, c.sz, c.tc, ms / reps);
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
@@ -654,6 +660,9 @@ int dirac_set_launch_config(const dirac_op* op, const dirac_launch* cfg) {
   LaunchCfg c{cfg->block_sites, cfg->rhs_per_thread, cfg->xcd_remap ? 1 : 0, cfg->lds ? 1 : 0,
               cfg->nt_store ? 1 : 0, cfg->tile_y, cfg->tile_z, cfg->t_chunk, 1};
   if (c.lds) {
+    if (cfg->xcd_remap < 0 || cfg->xcd_remap > 7)
+      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: xcd_remap of the streaming kernel is a 3-bit mask");
+    c.remap = cfg->xcd_remap;
     if (o.nrhs != 1) return set_error(DIRAC_EINVAL, "dirac_set_launch_config: the streaming kernel takes nrhs = 1");
     if (!stream_fits(o.g, c.sy, c.sz, c.tc))
       return set_error(DIRAC_EINVAL,

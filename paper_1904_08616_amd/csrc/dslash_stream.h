@@ -11,7 +11,10 @@
 // Every spinor is therefore read from memory about once per sweep instead
 // of up to nine times, and every U_t once instead of twice; the U_x, U_y,
 // U_z of a site are read by its own thread and again (backward hop) by the
-// neighbour thread a few instructions later, which the caches serve.
+// neighbour thread a few instructions later, which the caches serve.  The
+// walk can run downwards in t as well (mirror image), so that the two
+// chunks on either side of a chunk boundary fetch the slices and links they
+// share at the same moment and the L2 serves the second reader.
 #pragma once
 
 #include "dslash_impl.h"
@@ -71,31 +74,247 @@ __device__ __forceinline__ void hop_apply(const M3<R>& u, const Cx<R> (&v)[12], 
 #ifndef DIRAC_STREAM_WAVES_F32
 #define DIRAC_STREAM_WAVES_F32 3
 #endif
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC>
-__global__ void __launch_bounds__(NC)
-__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? 2 : DIRAC_STREAM_WAVES_F32)))
-k_dslash_stream(DslashArgs a) {
+
+// Launch-order flags of the streaming kernel (DslashArgs::remap bits).
+constexpr int kStreamXcd = 1;   // XCD-contiguous block order
+constexpr int kStreamTFast = 2; // t-chunks fastest in the block order
+constexpr int kStreamAlt = 4;   // odd t-chunks walk downwards
+
+// One block's walk over the slices [t0, t1) of its tile, upwards (DOWN =
+// false) or downwards.  The t-link between the centre slice t and the next
+// slice tn = t +- 1 is loaded once per step: walking up it is U_t(n), giving
+// the forward hop U (1 - S gamma_t) psi(n + t) of site n and the backward
+// hop U^dag (1 + S gamma_t) psi(n) carried into n + t; walking down it is
+// U_t(n - t), giving the backward hop of n and the forward hop
+// U (1 - S gamma_t) psi(n) carried into n - t.  Neighbouring chunks that walk
+// in opposite directions read their shared halo slice and link at the same
+// time (both at the start, or both at the end of the walk).
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN>
+__device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, int z, int yl, int zl, int t0,
+                                            int t1, char* lds_raw, double& val) {
   using SI = SpinFmt<PI>;
   using SO = SpinFmt<PO>;
   using LF = LinkFmt<PI, LK>;
   using Rl = typename SI::R;
   using Ro = typename SO::R;
   constexpr int S = DAG ? -1 : 1;
-  extern __shared__ __align__(16) char lds_raw[];
+  constexpr int SC = DOWN ? -S : S;  // projector sign of the carried hop
   const Geom g = a.g;
   const int Vh = g.Vh;
   const int BY = a.sy, BZ = a.sz;
+  const int tid = threadIdx.x;
+  const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
+  const Rsrc in = make_rsrc(a.in, a.field_bytes);
+  const int xp = (x + 1 == g.X) ? 0 : x + 1, xm = (x == 0) ? g.X - 1 : x - 1;
+  const int yp = (y + 1 == g.Y) ? 0 : y + 1, ym = (y == 0) ? g.Y - 1 : y - 1;
+  const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
+  const int col_xp = tid - x + xp, col_xm = tid - x + xm;
+  const bool in_yp = yl + 1 < BY, in_ym = yl > 0, in_zp = zl + 1 < BZ, in_zm = zl > 0;
+  // LDS: two slice buffers [2][12][NC] (slice t is read while the next one
+  // is written) and, in float64, a private slot per thread for the carried hop.
+  Cx<Rl>* const lbase = reinterpret_cast<Cx<Rl>*>(lds_raw);
+  Cx<Rl>* const wslot = lbase + 24 * NC + tid;
+  constexpr bool kWtInLds = (PI == DIRAC_F64);
+  const int ts = DOWN ? t1 - 1 : t0;  // first centre slice
+  const int nsteps = t1 - t0;
 
+  // prologue: centre psi(ts) into buffer 0 and the hop carried into ts from
+  // the slice before it in walking order, kept as w = U^(dag) h (12 reals)
+  Cx<Rl> Wt[2][3];
+  {
+    int p, i;
+    site_pi(g, x, y, z, ts, p, i);
+    Cx<Rl> v[12];
+    SI::load(in, Vh, p, i, v);
+    StreamLds<PI, NC>{lbase}.put(tid, v);
+    const int tq = DOWN ? ((ts + 1 == g.T) ? 0 : ts + 1) : ((ts == 0) ? g.T - 1 : ts - 1);
+    int pq, iq;
+    site_pi(g, x, y, z, tq, pq, iq);
+    SI::load(in, Vh, pq, iq, v);
+    M3<Rl> u;
+    Cx<Rl> h[2][3];
+    project<3, SC>(v, h);
+    if constexpr (DOWN) {
+      LF::load(Ur, Vh, p, 3, i, u);  // U_t(ts) links ts and ts + 1
+      su3_mul(u, h, Wt);
+    } else {
+      LF::load(Ur, Vh, pq, 3, iq, u);  // U_t(ts - 1) links ts - 1 and ts
+      su3_dag_mul(u, h, Wt);
+    }
+    if constexpr (kWtInLds) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
+    }
+  }
+  __syncthreads();
+
+#pragma nounroll
+  for (int s = 0; s < nsteps; ++s) {
+    const int t = DOWN ? ts - s : ts + s;
+    const int b = s & 1;
+    const StreamLds<PI, NC> cur_s{lbase + b * 12 * NC};        // slice t
+    const StreamLds<PI, NC> nxt_s{lbase + (b ^ 1) * 12 * NC};  // slice tn
+    int p, i;
+    site_pi(g, x, y, z, t, p, i);
+    const int tn = DOWN ? ((t == 0) ? g.T - 1 : t - 1) : ((t + 1 == g.T) ? 0 : t + 1);
+    int pn, in_;
+    site_pi(g, x, y, z, tn, pn, in_);
+    Cx<Rl> nxt[12];
+    SI::load(in, Vh, pn, in_, nxt);
+
+    Cx<Rl> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {Rl(0), Rl(0)};
+    if constexpr (kWtInLds) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Wt[k / 3][k % 3] = wslot[k * NC];
+    }
+    reconstruct_add<3, SC>(acc, Wt);  // the t hop carried from the previous slice
+    {
+      M3<Rl> u;
+      Cx<Rl> v[12];
+      // x: both neighbours are in the tile (it spans all of x)
+      LF::load(Ur, Vh, p, 0, i, u);
+      cur_s.get(col_xp, v);
+      hop_apply<0, DAG, true>(u, v, acc);
+      {
+        int pb, ib;
+        site_pi(g, xm, y, z, t, pb, ib);
+        LF::load(Ur, Vh, pb, 0, ib, u);
+      }
+      cur_s.get(col_xm, v);
+      hop_apply<0, DAG, false>(u, v, acc);
+      nxt_s.put(tid, nxt);  // psi(tn) waits in LDS for the t hop and the next step
+      pin12(acc);
+      // y
+      LF::load(Ur, Vh, p, 1, i, u);
+      if (in_yp) {
+        cur_s.get(tid + g.X, v);
+      } else {
+        int pf, jf;
+        site_pi(g, x, yp, z, t, pf, jf);
+        SI::load(in, Vh, pf, jf, v);
+      }
+      hop_apply<1, DAG, true>(u, v, acc);
+      {
+        int pb, ib;
+        site_pi(g, x, ym, z, t, pb, ib);
+        LF::load(Ur, Vh, pb, 1, ib, u);
+        if (in_ym)
+          cur_s.get(tid - g.X, v);
+        else
+          SI::load(in, Vh, pb, ib, v);
+      }
+      hop_apply<1, DAG, false>(u, v, acc);
+      pin12(acc);
+      // z
+      LF::load(Ur, Vh, p, 2, i, u);
+      if (in_zp) {
+        cur_s.get(tid + g.X * BY, v);
+      } else {
+        int pf, jf;
+        site_pi(g, x, y, zp, t, pf, jf);
+        SI::load(in, Vh, pf, jf, v);
+      }
+      hop_apply<2, DAG, true>(u, v, acc);
+      {
+        int pb, ib;
+        site_pi(g, x, y, zm, t, pb, ib);
+        LF::load(Ur, Vh, pb, 2, ib, u);
+        if (in_zm)
+          cur_s.get(tid - g.X * BY, v);
+        else
+          SI::load(in, Vh, pb, ib, v);
+      }
+      hop_apply<2, DAG, false>(u, v, acc);
+      pin12(acc);
+      // t: the hop from psi(tn) now, and the hop from psi(t) carried to tn
+      if constexpr (DOWN)
+        LF::load(Ur, Vh, pn, 3, in_, u);  // U_t(n - t)
+      else
+        LF::load(Ur, Vh, p, 3, i, u);  // U_t(n)
+      nxt_s.get(tid, v);
+      hop_apply<3, DAG, !DOWN>(u, v, acc);
+      cur_s.get(tid, v);
+      Cx<Rl> h[2][3];
+      project<3, SC>(v, h);
+      if constexpr (DOWN)
+        su3_mul(u, h, Wt);
+      else
+        su3_dag_mul(u, h, Wt);
+      if constexpr (kWtInLds) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
+      }
+    }
+
+    // epilogue at site (p, i) with centre psi(t)
+    Cx<Rl> cur[12];
+    cur_s.get(tid, cur);
+    const Rl m4 = (Rl)a.mass4;
+    Cx<Ro> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
+    const Rsrc orsrc = make_rsrc(a.out, a.out_bytes);
+    if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+      if (a.nt_store)
+        SO::template store<2>(orsrc, Vh, p, i, o);
+      else
+        SO::template store<0>(orsrc, Vh, p, i, o);
+      if constexpr (EPI == kEpiStoreNorm) {
+        Cx<Ro> q[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = o[k];
+        SO::round(q);
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) sum += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+        val += sum;
+      }
+    } else {
+      const Ro cf = a.sub_alpha ? (Ro)a.red.state[0].alpha : Ro(1);
+      Cx<Ro> d[12];
+      SO::load(make_rsrc(a.src, a.out_bytes), Vh, p, i, d);
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        d[k].re = fma(-cf, o[k].re, d[k].re);
+        d[k].im = fma(-cf, o[k].im, d[k].im);
+        sum += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+      }
+      SO::template store<0>(orsrc, Vh, p, i, d);
+      val += sum;
+    }
+    __syncthreads();  // slice tn complete; slice t no longer read
+  }
+}
+
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC>
+__global__ void __launch_bounds__(NC)
+__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? 2 : DIRAC_STREAM_WAVES_F32)))
+k_dslash_stream(DslashArgs a) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const Geom g = a.g;
+  const int BY = a.sy, BZ = a.sz;
   const int tid = threadIdx.x;
   const int x = tid % g.X;
   const int yl = (tid / g.X) % BY;
   const int zl = tid / (g.X * BY);
   const int nty = g.Y / BY, ntz = g.Z / BZ;
   const int nblocks = a.ntiles;
-  const int l = xcd_tile(blockIdx.x, nblocks, a.remap);
-  const int ty = l % nty;
-  const int tz = (l / nty) % ntz;
-  const int tt = l / (nty * ntz);
+  const int ntt = nblocks / (nty * ntz);
+  const int l = xcd_tile(blockIdx.x, nblocks, a.remap & kStreamXcd);
+  int ty, tz, tt;
+  if (a.remap & kStreamTFast) {
+    tt = l % ntt;
+    ty = (l / ntt) % nty;
+    tz = l / (ntt * nty);
+  } else {
+    ty = l % nty;
+    tz = (l / nty) % ntz;
+    tt = l / (nty * ntz);
+  }
   const int y = ty * BY + yl, z = tz * BZ + zl;
   const int t0 = tt * a.tc;
   const int t1 = min(t0 + a.tc, g.T);
@@ -105,179 +324,10 @@ k_dslash_stream(DslashArgs a) {
   if (a.gate == kGateActive) on = a.red.state[0].active != 0;
   double vals[1][1] = {{0.0}};
   if (on) {
-    const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
-    const Rsrc in = make_rsrc(a.in, a.field_bytes);
-    const int xp = (x + 1 == g.X) ? 0 : x + 1, xm = (x == 0) ? g.X - 1 : x - 1;
-    const int yp = (y + 1 == g.Y) ? 0 : y + 1, ym = (y == 0) ? g.Y - 1 : y - 1;
-    const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
-    const int col_xp = tid - x + xp, col_xm = tid - x + xm;
-    const bool in_yp = yl + 1 < BY, in_ym = yl > 0, in_zp = zl + 1 < BZ, in_zm = zl > 0;
-    // LDS: two slice buffers [2][12][NC] (slice t is read while t+1 is
-    // written) and, in float64, a private slot per thread for the carried hop.
-    Cx<Rl>* const lbase = reinterpret_cast<Cx<Rl>*>(lds_raw);
-    Cx<Rl>* const wslot = lbase + 24 * NC + tid;
-    constexpr bool kWtInLds = (PI == DIRAC_F64);
-
-    // prologue: centre psi(t0) into buffer 0 and the backward-t hop carried
-    // into t0, kept as its half spinor w = U^dag h (12 reals)
-    Cx<Rl> Wt[2][3];
-    {
-      int p, i;
-      site_pi(g, x, y, z, t0, p, i);
-      Cx<Rl> v[12];
-      SI::load(in, Vh, p, i, v);
-      StreamLds<PI, NC>{lbase}.put(tid, v);
-      const int tm = (t0 == 0) ? g.T - 1 : t0 - 1;
-      int pm, im;
-      site_pi(g, x, y, z, tm, pm, im);
-      SI::load(in, Vh, pm, im, v);
-      M3<Rl> u;
-      LF::load(Ur, Vh, pm, 3, im, u);
-      Cx<Rl> h[2][3];
-      project<3, S>(v, h);
-      su3_dag_mul(u, h, Wt);
-      if constexpr (kWtInLds) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
-      }
-    }
-    __syncthreads();
-
-#pragma nounroll
-    for (int t = t0; t < t1; ++t) {
-      const int b = (t - t0) & 1;
-      const StreamLds<PI, NC> cur_s{lbase + b * 12 * NC};       // slice t
-      const StreamLds<PI, NC> nxt_s{lbase + (b ^ 1) * 12 * NC}; // slice t+1
-      int p, i;
-      site_pi(g, x, y, z, t, p, i);
-      const int tn = (t + 1 == g.T) ? 0 : t + 1;
-      Cx<Rl> nxt[12];
-      {
-        int pn, in_;
-        site_pi(g, x, y, z, tn, pn, in_);
-        SI::load(in, Vh, pn, in_, nxt);
-      }
-
-      Cx<Rl> acc[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) acc[k] = {Rl(0), Rl(0)};
-      if constexpr (kWtInLds) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Wt[k / 3][k % 3] = wslot[k * NC];
-      }
-      reconstruct_add<3, S>(acc, Wt);  // backward t hop
-      {
-        M3<Rl> u;
-        Cx<Rl> v[12];
-        // x: both neighbours are in the tile (it spans all of x)
-        LF::load(Ur, Vh, p, 0, i, u);
-        cur_s.get(col_xp, v);
-        hop_apply<0, DAG, true>(u, v, acc);
-        {
-          int pb, ib;
-          site_pi(g, xm, y, z, t, pb, ib);
-          LF::load(Ur, Vh, pb, 0, ib, u);
-        }
-        cur_s.get(col_xm, v);
-        hop_apply<0, DAG, false>(u, v, acc);
-        nxt_s.put(tid, nxt);  // psi(t+1) waits in LDS for the t hop and the next slice
-        pin12(acc);
-        // y
-        LF::load(Ur, Vh, p, 1, i, u);
-        if (in_yp) {
-          cur_s.get(tid + g.X, v);
-        } else {
-          int pf, jf;
-          site_pi(g, x, yp, z, t, pf, jf);
-          SI::load(in, Vh, pf, jf, v);
-        }
-        hop_apply<1, DAG, true>(u, v, acc);
-        {
-          int pb, ib;
-          site_pi(g, x, ym, z, t, pb, ib);
-          LF::load(Ur, Vh, pb, 1, ib, u);
-          if (in_ym)
-            cur_s.get(tid - g.X, v);
-          else
-            SI::load(in, Vh, pb, ib, v);
-        }
-        hop_apply<1, DAG, false>(u, v, acc);
-        pin12(acc);
-        // z
-        LF::load(Ur, Vh, p, 2, i, u);
-        if (in_zp) {
-          cur_s.get(tid + g.X * BY, v);
-        } else {
-          int pf, jf;
-          site_pi(g, x, y, zp, t, pf, jf);
-          SI::load(in, Vh, pf, jf, v);
-        }
-        hop_apply<2, DAG, true>(u, v, acc);
-        {
-          int pb, ib;
-          site_pi(g, x, y, zm, t, pb, ib);
-          LF::load(Ur, Vh, pb, 2, ib, u);
-          if (in_zm)
-            cur_s.get(tid - g.X * BY, v);
-          else
-            SI::load(in, Vh, pb, ib, v);
-        }
-        hop_apply<2, DAG, false>(u, v, acc);
-        pin12(acc);
-        // t: forward hop with psi(t+1); the backward hop for t+1 from U_t(n), psi(n)
-        LF::load(Ur, Vh, p, 3, i, u);
-        nxt_s.get(tid, v);
-        hop_apply<3, DAG, true>(u, v, acc);
-        cur_s.get(tid, v);
-        Cx<Rl> h[2][3];
-        project<3, S>(v, h);
-        su3_dag_mul(u, h, Wt);
-        if constexpr (kWtInLds) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
-        }
-      }
-
-      // epilogue at site (p, i) with centre psi(t)
-      Cx<Rl> cur[12];
-      cur_s.get(tid, cur);
-      const Rl m4 = (Rl)a.mass4;
-      Cx<Ro> o[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k)
-        o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
-      const Rsrc orsrc = make_rsrc(a.out, a.out_bytes);
-      if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
-        if (a.nt_store)
-          SO::template store<2>(orsrc, Vh, p, i, o);
-        else
-          SO::template store<0>(orsrc, Vh, p, i, o);
-        if constexpr (EPI == kEpiStoreNorm) {
-          Cx<Ro> q[12];
-#pragma unroll
-          for (int k = 0; k < 12; ++k) q[k] = o[k];
-          SO::round(q);
-          double s = 0.0;
-#pragma unroll
-          for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
-          vals[0][0] += s;
-        }
-      } else {
-        const Ro cf = a.sub_alpha ? (Ro)a.red.state[0].alpha : Ro(1);
-        Cx<Ro> d[12];
-        SO::load(make_rsrc(a.src, a.out_bytes), Vh, p, i, d);
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          d[k].re = fma(-cf, o[k].re, d[k].re);
-          d[k].im = fma(-cf, o[k].im, d[k].im);
-          s += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
-        }
-        SO::template store<0>(orsrc, Vh, p, i, d);
-        vals[0][0] += s;
-      }
-      __syncthreads();  // slice t+1 complete; slice t no longer read
-    }
+    if ((a.remap & kStreamAlt) && (tt & 1))
+      stream_walk<PI, PO, LK, DAG, EPI, NC, true>(a, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+    else
+      stream_walk<PI, PO, LK, DAG, EPI, NC, false>(a, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
   }
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, 0, 1, blockIdx.x, nblocks);
 }

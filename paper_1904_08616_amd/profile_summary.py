@@ -2,6 +2,8 @@
 
     python -m paper_1904_08616_amd.profile_summary trace RUN.db --command "..."
         per-kernel call count and duration statistics (the --stats table)
+    python -m paper_1904_08616_amd.profile_summary pmc RUN.db [RUN2.db ...] --kernel NAME --command "..."
+        average value per dispatch of every counter collected, for kernels matching NAME
     python -m paper_1904_08616_amd.profile_summary counters --fetch F.db --write W.db \
         --kernel k_dslash_stream --fetch-command "..." --write-command "..." [--json OUT]
         FETCH_SIZE / WRITE_SIZE per dispatch of one kernel, scaled by what the
@@ -86,6 +88,19 @@ def counter_report(fetch_db, write_db, kernel, fetch_cmd, write_cmd):
     return "\n".join(lines), res
 
 
+def pmc_report(dbs, command, kernels):
+    """Average value per dispatch of every counter in the runs, per kernel."""
+    out = [f"command: {command}", "", "average per dispatch (dispatches)", ""]
+    for db in dbs:
+        c = sqlite3.connect(db)
+        rows = c.execute("select name, counter_name, count(*), avg(counter_value), max(counter_value) "
+                         "from pmc_events group by name, counter_name order by name, counter_name").fetchall()
+        for r in rows:
+            if any(k in r[0] for k in kernels):
+                out.append("%-26s %16.1f  (n %3d, max %14.1f)  %s" % (r[1], r[3], r[2], r[4], r[0]))
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -100,9 +115,16 @@ def main(argv=None):
     c.add_argument("--write-command", required=True)
     c.add_argument("--json")
     c.add_argument("--launch", help="launch configuration (JSON) the counters were taken with")
+    q = sub.add_parser("pmc")
+    q.add_argument("dbs", nargs="+")
+    q.add_argument("--command", required=True)
+    q.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args(argv)
     if a.mode == "trace":
         print(trace_report(a.db, a.command))
+        return 0
+    if a.mode == "pmc":
+        print(pmc_report(a.dbs, a.command, a.kernel))
         return 0
     text, res = counter_report(a.fetch, a.write, a.kernel, a.fetch_command, a.write_command)
     print(text)

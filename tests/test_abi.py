@@ -129,6 +129,11 @@ def test_launch_config_validation():
     got = abi.DiracLaunch()
     assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
     assert (got.lds, got.tile_y, got.tile_z, got.t_chunk, got.tuned) == (1, 4, 4, 2, 1)
+    # the streaming kernel's order flags are a 3-bit mask
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 8, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 7, 0, 1, 4, 4, 2, 0))) == abi.OK
+    assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
+    assert got.xcd_remap == 7
     assert lib.dirac_multi_apply(0, None, None, None, None, 0, None) == abi.EINVAL
     assert lib.dirac_multi_apply(9, None, None, None, None, 0, None) == abi.EINVAL
 

@@ -198,14 +198,16 @@ def test_cg_with_split_kernels(inner, R):
     assert true_res(U, eta, x, m) < 1e-10
 
 
+@pytest.mark.parametrize("remap", [1, 7])
 @pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
-def test_cg_with_stream_kernels(inner):
+def test_cg_with_stream_kernels(inner, remap):
     # the t-streaming Dslash with its norm and residual-update epilogues
+    # (remap 7: t-chunks fastest and odd chunks walking down in t)
     dims = (16, 8, 4, 8)
     U, eta = inputs(dims, "exp", seed=11)
     m = 0.1
     for prec in ("f64", "f32", "f16s"):
-        D.Operator(dims, m, prec, 12).set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=3)
+        D.Operator(dims, m, prec, 12).set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=3, xcd_remap=remap)
     x, st = solve(U, eta, m, link=12, inner=inner)
     assert st[0]["status"] == abi.OK
     assert true_res(U, eta, x, m) < 1e-10

@@ -210,7 +210,8 @@ def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
     pi = op.pack_spinor(cuda(psi))
     f = wilson.dslash_dagger if dagger else wilson.dslash
     ref = f(lowprec.store_links(U, prec), lowprec.store(psi, prec), m)
-    for remap in (0, 1):
+    # remap bits: XCD order, t-chunks fastest, odd chunks walking down in t
+    for remap in range(8):
         op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc, xcd_remap=remap)
         assert op.launch_config()["lds"] == 1
         got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
