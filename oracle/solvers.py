@@ -127,6 +127,14 @@ def mixed_cg(U, eta, m_q, tol=1e-10, inner_fmt="f32", delta=None, k_max=10000,
     in binary32 (all f64 when inner_fmt == "f64").  Reductions are float64.
     Returns (x, info) with info = dict(status, iters, outer, true_rel_res,
     history) where history lists the true relative residual after each cycle.
+
+    The inner iteration count is left open by the paper.  Reading: the first
+    cycle runs until sqrt(rho) < delta or k_max; every later cycle, which
+    again starts from a unit residual, may take at most twice the first
+    cycle's count (at least 50).  A cycle that stops at that cap means the
+    low-precision operator is too far from the float64 one for the target
+    (e.g. bfloat16 links at a small quark mass); after two such cycles in a
+    row the solve continues in float64, as after six stalled cycles.
     """
     if delta is None:
         delta = 1e-3 if inner_fmt in ("f32", "f64") else 0.1
@@ -149,6 +157,8 @@ def mixed_cg(U, eta, m_q, tol=1e-10, inner_fmt="f32", delta=None, k_max=10000,
     total = 0
     outer = 0
     stall = 0
+    capped = 0
+    n_first = None
     s_best = s
     history = [s / eta_norm]
     status = ENOCONV
@@ -166,6 +176,7 @@ def mixed_cg(U, eta, m_q, tol=1e-10, inner_fmt="f32", delta=None, k_max=10000,
             p = lowprec.store(r0, fmt)
         psi = np.zeros_like(r0)
         n = 0
+        n_cap = k_max if n_first is None else min(k_max, max(2 * n_first, 50))
         while True:
             q = A_low(p)
             pq = float(np.real(inner(p, q)))
@@ -179,10 +190,14 @@ def mixed_cg(U, eta, m_q, tol=1e-10, inner_fmt="f32", delta=None, k_max=10000,
             p = lowprec.store(r0 + (rho_new / rho) * p, fmt)
             rho = rho_new
             n += 1
-            if np.sqrt(rho) < delta or n >= k_max or s * np.sqrt(rho) < 0.5 * tol * eta_norm:
+            if np.sqrt(rho) < delta or n >= n_cap or s * np.sqrt(rho) < 0.5 * tol * eta_norm:
                 break
             if total + n >= max_iter:
                 break
+        if n_first is None:
+            n_first = n
+        hit_cap = n >= n_cap and np.sqrt(rho) >= delta
+        capped = capped + 1 if hit_cap else 0
         total += n
         if status == EBREAKDOWN:
             break
@@ -200,11 +215,12 @@ def mixed_cg(U, eta, m_q, tol=1e-10, inner_fmt="f32", delta=None, k_max=10000,
             stall += 1
             if stall == 3:
                 p_k = None
-            elif stall >= 6 and fmt != "f64":
-                fmt = "f64"
-                vec_fmt = "f64"
-                A_low = low_operator(U, m_q, "f64")
-                p_k = None
+        if fmt != "f64" and (stall >= 6 or capped >= 2):
+            fmt = "f64"
+            vec_fmt = "f64"
+            A_low = low_operator(U, m_q, "f64")
+            p_k = None
+            n_first = None
     true_res = s / eta_norm
     if true_res < tol:
         status = OK

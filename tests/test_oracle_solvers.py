@@ -140,3 +140,22 @@ def test_bf16_rounding_matches_torch():
     ours = lowprec._round_bf16(x)
     ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(ours, ref)
+
+
+def test_mixed_cg_inner_cap_falls_back_for_bf16():
+    # bfloat16 links perturb D by ~2^-9 relative, about the mass gap at
+    # m = 0.05: the low-precision inner solves cannot reach the target.  Later
+    # cycles are capped at twice the first cycle's count and two capped
+    # cycles hand over to float64, so the solve still converges quickly.
+    dims = (4, 4, 4, 4)
+    g = synth.rng(3)
+    om = synth.gauge_transform_haar(dims, g)
+    U = synth.links_pure_gauge(om)
+    eta = synth.spinor_gauss(dims, g)
+    x, info = solvers.mixed_cg(U, eta, 0.05, tol=1e-10, inner_fmt="bf16s", max_iter=20000)
+    assert info["status"] == solvers.OK
+    assert info["iters"] < 1000
+    assert info["true_rel_res"] < 1e-10
+    omd = np.conj(np.swapaxes(om, -1, -2))
+    xref = synth.gauge_transform_spinor(freefield.solve_ddagd(synth.gauge_transform_spinor(eta, omd), 0.05), om)
+    assert np.linalg.norm((x - xref).ravel()) / np.linalg.norm(xref.ravel()) < freefield.condition_number(0.05) * 2e-10
