@@ -138,7 +138,11 @@ int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x
  *   inner_delta : inner stop when ||r_inner|| < inner_delta (the inner
  *                 residual starts at norm 1); <= 0 picks 1e-3 (F32) or
  *                 0.1 (F16S/BF16S).
- *   inner_kmax  : cap on one inner solve (<= 0: 10000).
+ *   inner_kmax  : cap on one inner solve (<= 0: 10000).  Every cycle after
+ *                 the first is further capped at twice the first cycle's
+ *                 iteration count (at least 50); two capped cycles in a row,
+ *                 or six cycles without progress, finish the solve with
+ *                 float64 CG from the current iterate.
  *   check_every : iterations launched between host convergence checks
  *                 (<= 0: automatic).
  */

@@ -22,7 +22,12 @@
 // ||r_inner|| < delta; the solution is updated x += s psi in float64.  The
 // search direction of the previous cycle is carried over after removing its
 // component along the new r0 and rescaling by beta_0 = s_new / (s_old rho_k)
-// (the reading of the carried direction p_0 = r0 + beta_0 p~).
+// (the reading of the carried direction p_0 = r0 + beta_0 p~).  The inner
+// iteration count is open in the paper: the first cycle runs to ||r|| < delta
+// (or inner_kmax); later cycles, which restart from a unit residual, may take
+// at most twice the first cycle's count.  Two capped cycles in a row, or six
+// cycles without progress, mean the low-precision operator cannot reach the
+// target and the solve finishes in float64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -249,7 +254,7 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
 
   std::vector<double> s(n), s_prev(n, 0.0), s_best(n), rho_k(n, 0.0);
   std::vector<bool> have_p(n, false), conv(n, false);
-  std::vector<int> stall(n, 0), used(n, 0);
+  std::vector<int> stall(n, 0), used(n, 0), capped(n, 0), n_first(n, -1), n_cap(n, kmax);
   *fallback = false;
 
   int rc = hip_status(zero(c.hi.g, n, PLO, c.st), "zero");
@@ -316,7 +321,9 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
       const double stop_a = delta * delta;
       const double stop_b = std::pow(0.5 * prm.tol * en[k] / std::max(s[k], 1e-300), 2);
       S.stop2 = std::max(stop_a, stop_b);
-      S.kmax = std::max(1, std::min(kmax, prm.max_iter - used[k]));
+      // every cycle after the first may take at most twice the first one's count
+      n_cap[k] = n_first[k] < 0 ? kmax : std::min(kmax, std::max(2 * n_first[k], 50));
+      S.kmax = std::max(1, std::min(n_cap[k], prm.max_iter - used[k]));
       S.iters = 0;
       S.done = conv[k] ? 1 : 0;
       S.active = 0;
@@ -338,6 +345,9 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
       stats[k].dslash_lo += 2 * S.iters;
       used[k] += S.iters;
       rho_k[k] = S.rho;
+      if (n_first[k] < 0) n_first[k] = S.iters;
+      const bool hit_cap = S.iters >= n_cap[k] && S.rho >= S.stop2;
+      capped[k] = hit_cap ? capped[k] + 1 : 0;
       // x += s psi
       S.coef[0] = s[k];
       S.coef[1] = 0.0;
@@ -378,8 +388,11 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
         stall[k] = 0;
       } else if (++stall[k] >= 3) {
         have_p[k] = false;  // restart without the carried direction
-        if (stall[k] >= 6) stagnated = true;
       }
+      // the low-precision operator is too far from the float64 one: six
+      // cycles without progress, or two inner solves in a row that stopped at
+      // their iteration cap
+      if (stall[k] >= 6 || capped[k] >= 2) stagnated = true;
     }
     if (stagnated) {
       *fallback = true;  // finish in float64

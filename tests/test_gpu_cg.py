@@ -109,6 +109,8 @@ def test_mixed_pure_gauge_closed_form(inner):
     err = rel_2(x, xref)
     print(f"pure gauge {inner}: iters {st[0]['iters']} outer {st[0]['outer']} err {err:.2e}")
     assert err <= freefield.condition_number(m) * 2e-10
+    # capped inner cycles hand a hopeless low precision over to float64
+    assert st[0]["iters"] <= 2000
 
 
 @pytest.mark.parametrize("inner", ["f32", "f16s"])
