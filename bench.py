@@ -166,6 +166,165 @@ def cg_time(torch, D, dims, U, eta, m_q, inner, link=18, tol=1e-10, reps=1):
     return best
 
 
+def cg_time_multi(torch, D, dims, U, src, m_q, inner, link=12, tol=1e-10):
+    """One batched solve over all right-hand sides of ``src`` [nrhs, ...]."""
+    nrhs = src.shape[0]
+    op = D.Operator(dims, m_q, "f64", link, nrhs)
+    Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    Ul = None
+    if inner != "f64":
+        Ul = op.like(prec=inner, link=link if inner == "f32" else 12, nrhs=nrhs).pack_gauge(
+            torch.from_numpy(U).cuda())
+    e = op.pack_spinor(torch.from_numpy(src).cuda())
+    D.cg(op, Ui, e, tol=tol, inner_prec=inner, U_lo=Ul)  # untimed: tuning, first touch
+    x = torch.zeros_like(e)
+    with Timer(torch) as t:
+        x, st = D.cg(op, Ui, e, x, tol=tol, inner_prec=inner, U_lo=Ul)
+    return {"ms": round(t.ms, 2), "iters_max": max(s["iters"] for s in st),
+            "true_rel_res_max": max(s["true_rel_res"] for s in st),
+            "all_converged": all(s["status"] == 0 for s in st)}
+
+
+def bench_multi_rhs(torch, D, steps, warmup):
+    """12 point sources (one per spin x colour) on 24^3 x 48, float32 with
+    12-real links: one 12-RHS Dslash against twelve single ones, and the
+    batched solve (mixed and float64) against twelve single float64 solves."""
+    import synth
+    dims = (24, 24, 24, 48)
+    V = int(np.prod(dims))
+    g = synth.rng(0)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)
+    out = {}
+    ms12, _, cfg12 = time_dslash(torch, D, dims, "f32", 12, U, src, max(20, steps // 8), 5, nrhs=12, m_q=0.05)
+    ms1, _, cfg1 = time_dslash(torch, D, dims, "f32", 12, U, src[0], max(20, steps // 8), 5, m_q=0.05)
+    b12 = site_bytes("f32", 12, 12) * V
+    out["dslash_24x24x24x48_f32_link12_12rhs"] = {
+        "ms": round(ms12, 4), "GB/s": round(b12 / (ms12 * 1e-3) / 1e9, 1),
+        "frac": round(b12 / (ms12 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "GFLOP/s": round(12 * FLOPS_PER_SITE * V / (ms12 * 1e-3) / 1e9, 1),
+        "vs_12_single_ms": round(12 * ms1, 4), "launch": cfg12, "single_launch": cfg1}
+    out["cg_24x24x24x48_m0.05_12_point_sources"] = {
+        "batched_f32_mixed": cg_time_multi(torch, D, dims, U, src, 0.05, "f32"),
+        "batched_f64": cg_time_multi(torch, D, dims, U, src, 0.05, "f64"),
+    }
+    seq = 0.0
+    iters = []
+    for k in range(12):
+        r = cg_time(torch, D, dims, U, src[k], 0.05, "f64", link=12)
+        seq += r["ms"]
+        iters.append(r["iters"])
+    out["cg_24x24x24x48_m0.05_12_point_sources"]["sequential_f64_ms"] = round(seq, 2)
+    out["cg_24x24x24x48_m0.05_12_point_sources"]["sequential_f64_iters_max"] = max(iters)
+    return out
+
+
+def bench_multi_lattice(torch, D, steps):
+    """One persistent hipGraph launch over 8^4, 12^4, 16^3 x 32 and 24^3 x 48
+    (float32, 12-real links, own seeds and masses) against four separate
+    autotuned launches."""
+    import synth
+    cases = [((8, 8, 8, 8), 0, 0.02), ((12, 12, 12, 12), 1, 0.08), ((16, 16, 16, 32), 2, 0.14),
+             ((24, 24, 24, 48), 3, 0.20)]
+    ops, Us, psis, chis = [], [], [], []
+    total = 0
+    for dims, seed, m in cases:
+        g = synth.rng(seed)
+        U = synth.links_exp(dims, 0.3, g)
+        psi = synth.spinor_gauss(dims, g)
+        op = D.Operator(dims, m, "f32", 12)
+        ops.append(op)
+        Us.append(op.pack_gauge(torch.from_numpy(U).cuda()))
+        psis.append(op.pack_spinor(torch.from_numpy(psi).cuda()))
+        chis.append(op.empty_spinor())
+        total += site_bytes("f32", 12) * int(np.prod(dims))
+    for op, u, p, c in zip(ops, Us, psis, chis):
+        if not op.launch_config()["tuned"]:
+            op.autotune(u, p, c)
+    reps = max(50, steps // 2)
+    for _ in range(5):
+        for op, u, p, c in zip(ops, Us, psis, chis):
+            op.apply(u, p, out=c)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            for op, u, p, c in zip(ops, Us, psis, chis):
+                op.apply(u, p, out=c)
+    sep = t.ms / reps
+    plan = D.MultiPlan(ops, Us, psis, chis)
+    for _ in range(5):
+        plan.launch()
+    with Timer(torch) as t:
+        for _ in range(reps):
+            plan.launch()
+    gr = t.ms / reps
+    plan.close()
+    return {"multi_lattice_f32_link12_graph": {
+        "lattices": [list(c[0]) for c in cases], "algorithmic_bytes": total,
+        "graph_ms": round(gr, 4), "graph_GB/s": round(total / (gr * 1e-3) / 1e9, 1),
+        "separate_ms": round(sep, 4), "separate_GB/s": round(total / (sep * 1e-3) / 1e9, 1)}}
+
+
+def bench_force(torch, D, steps):
+    """Link force (the backward of D with respect to U) and one autograd
+    forward + backward of chi = D(U) psi on 16^4 in float64."""
+    import synth
+    dims = (16, 16, 16, 16)
+    V = int(np.prod(dims))
+    g = synth.rng(0)
+    U = synth.links_exp(dims, 0.3, g)
+    psi = synth.spinor_gauss(dims, g)
+    gchi = synth.spinor_gauss(dims, g)
+    op = D.Operator(dims, 0.1, "f64", 18)
+    pi = op.pack_spinor(torch.from_numpy(psi).cuda())
+    gi = op.pack_spinor(torch.from_numpy(gchi).cuda())
+    F = torch.zeros(op.gauge_shape(), dtype=torch.complex128, device="cuda")
+    for _ in range(5):
+        op.force(gi, pi, out=F)
+    reps = max(50, steps // 2)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            op.force(gi, pi, out=F)
+    ms = t.ms / reps
+    fb = V * (2 * 192 + 4 * 9 * 16)  # g and psi read once, 4 complex128 3x3 written
+    Ut = torch.from_numpy(U).cuda().requires_grad_(True)
+    pt = torch.from_numpy(psi).cuda().requires_grad_(True)
+    gt = torch.from_numpy(gchi).cuda()
+    for _ in range(2):
+        D.DiracApply.apply(Ut, pt, 0.1).backward(gt)
+    with Timer(torch) as t:
+        for _ in range(10):
+            D.DiracApply.apply(Ut, pt, 0.1).backward(gt)
+    return {"force_16x16x16x16_f64": {"ms": round(ms, 4), "GB/s": round(fb / (ms * 1e-3) / 1e9, 1),
+                                      "frac": round(fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "autograd_dirac_apply_16x16x16x16_f64_fwd_bwd_ms": round(t.ms / 10, 3)}
+
+
+def bench_blas(torch, D, steps):
+    """dirac_field_dot (host result, so one synchronisation per call) and
+    dirac_field_axpy on float64 fields of 32^3 x 64."""
+    dims = (32, 32, 32, 64)
+    V = int(np.prod(dims))
+    op = D.Operator(dims, 0.02, "f64", 18)
+    nb = op.spinor_bytes()
+    a = torch.randn(nb // 8, dtype=torch.float64, device="cuda").view(torch.uint8)
+    b = torch.randn(nb // 8, dtype=torch.float64, device="cuda").view(torch.uint8)
+    reps = max(20, steps // 8)
+    for _ in range(3):
+        op.dot(a, b)
+        op.axpy(0.5, a, b)
+    with Timer(torch) as t:
+        for _ in range(reps):
+            op.dot(a, b)
+    dot_ms = t.ms / reps
+    with Timer(torch) as t:
+        for _ in range(reps):
+            op.axpy(1e-3, a, b)
+    axpy_ms = t.ms / reps
+    return {"blas_32x32x32x64_f64": {
+        "dot_ms": round(dot_ms, 4), "dot_GB/s": round(2 * 192 * V / (dot_ms * 1e-3) / 1e9, 1),
+        "axpy_ms": round(axpy_ms, 4), "axpy_GB/s": round(3 * 192 * V / (axpy_ms * 1e-3) / 1e9, 1)}}
+
+
 def copy_ceiling(torch, gib=1.0, reps=5):
     """A plain device-to-device copy of known size: the measured bandwidth
     ceiling, and the reference kernel for scaling the HBM byte counters."""
@@ -329,6 +488,16 @@ def main(argv=None):
                 extra[f"cg_32x32x32x64_m0.02_{inner}_link{link}"] = cg_time(torch, D, big, Ub, pb, 0.02, inner,
                                                                             link=link)
             del Ub, pb
+            torch.cuda.empty_cache()
+            log("multi-RHS 24^3x48")
+            extra.update(bench_multi_rhs(torch, D, a.steps, a.warmup))
+            torch.cuda.empty_cache()
+            log("multi-lattice graph")
+            extra.update(bench_multi_lattice(torch, D, a.steps))
+            log("force and autograd 16^4")
+            extra.update(bench_force(torch, D, a.steps))
+            log("BLAS-1 32^3x64")
+            extra.update(bench_blas(torch, D, a.steps))
         except Exception as e:  # report, but keep the headline
             extra["error"] = repr(e)
     if extra:

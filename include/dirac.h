@@ -206,14 +206,20 @@ int dirac_force(const dirac_op* op, const void* g_int, const void* psi_int, void
 
 /* Apply D (dagger = 0) or D^dagger (dagger = 1) on up to 8 independent
  * lattices (own geometry, links and m_q; one shared precision and link
- * storage; nrhs = 1) in ONE persistent kernel launch that walks a work list
- * of (lattice, tile) pairs.  ops, U, psi, chi are host arrays of n entries. */
+ * storage; nrhs = 1) in ONE kernel launch that walks a work list of
+ * (lattice, tile) pairs.  ops, U, psi, chi are host arrays of n entries.
+ * The launch form is either t-streaming tiles (each lattice its largest tile
+ * of at most 256 columns, one t_chunk for all) or per-site blocks: the form
+ * timed fastest by dirac_multi_plan_create for the same set of lattices,
+ * else streaming with t_chunk 4 when every lattice has a tile. */
 int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U,
                       const void* const* psi, void* const* chi, int32_t dagger, void* stream);
 
-/* Capture dirac_multi_apply with these arguments into a hipGraph once and
- * return an opaque plan (host) that replays it with dirac_plan_launch.  The
- * plan keeps the pointers: the buffers must outlive it. */
+/* Time the launch forms of dirac_multi_apply on these buffers and stream
+ * (chi is overwritten; the stream is synchronised), keep the fastest for
+ * this set of lattices, capture it into a hipGraph once and return an opaque
+ * plan (host) that replays it with dirac_plan_launch.  The plan keeps the
+ * pointers: the buffers must outlive it. */
 int dirac_multi_plan_create(int32_t n, const dirac_op* ops, const void* const* U,
                             const void* const* psi, void* const* chi, int32_t dagger,
                             void* stream, void** plan_out);
@@ -229,9 +235,11 @@ int dirac_plan_destroy(void* plan);
  *     each block of 64 sites, one direction pair per wave, partial spinors
  *     combined in LDS (nrhs = 1; for lattices too small to fill the device);
  *   - t-streaming (lds = 1): a block owns all of x times tile_y rows times
- *     tile_z planes (128 or 256 columns) and walks t_chunk time slices; the
- *     current slice is staged in LDS and the t neighbours stay in registers
- *     (nrhs = 1; tile_y | Ly and tile_z | Lz).
+ *     tile_z planes (32 to 256 columns, in a block of 128 or 256 threads)
+ *     and walks t_chunk time slices; the current slice is staged in LDS and
+ *     the t neighbours stay in registers (tile_y | Ly and tile_z | Lz; one
+ *     block per tile and right-hand side, the blocks of a tile adjacent so
+ *     that they share its links in the L2).
  * xcd_remap orders tiles so that each XCD sweeps one contiguous region
  * (0 or 1).  For the t-streaming kernel it is a mask: bit 0 that XCD order,
  * bit 1 t-chunks fastest in the block order, bit 2 odd t-chunks walk down in

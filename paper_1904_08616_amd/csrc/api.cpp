@@ -109,8 +109,8 @@ static std::vector<DslashEntry>& dslash_entries() {
 
 int run_dslash(int pin, int pout, int link, int dag, int epi, const LaunchCfg& c, DslashArgs a,
                hipStream_t st) {
-  // the streaming kernel takes one right-hand side on tiles that divide the lattice
-  const bool stream = c.lds && a.nrhs == 1 && stream_fits(a.g, c.sy, c.sz, c.tc);
+  // the streaming kernel takes tiles that divide the lattice (one block per tile and rhs)
+  const bool stream = c.lds && stream_fits(a.g, c.sy, c.sz, c.tc);
   const int key = stream ? 0 : (c.lds ? 1 : c.R);
   for (const DslashEntry& e : dslash_entries()) {
     if (e.pin == pin && e.pout == pout && e.link == link && e.dag == dag && e.epi == epi && e.rpt == key) {
@@ -470,12 +470,41 @@ int dirac_force(const dirac_op* op, const void* g_int, const void* psi_int, void
                     "force");
 }
 
-int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U, const void* const* psi,
-                      void* const* chi, int32_t dagger, void* stream) {
-  clear_error();
+// Launch form of a set of lattices: the one timed fastest when a plan was
+// made for the same set, else t-streaming with t_chunk 4 when every lattice
+// has a streaming tile, else the per-site form.
+namespace {
+std::mutex g_multi_mu;
+std::map<std::string, MultiCfg> g_multi_cfg;
+
+std::string multi_key(int n, const OpInfo* infos) {
+  std::string k;
+  for (int i = 0; i < n; ++i) k += cfg_key(infos[i]) + ";";
+  return k;
+}
+
+bool multi_stream_possible(int n, const OpInfo* infos) {
+  for (int i = 0; i < n; ++i) {
+    int sy, sz;
+    if (!multi_stream_tile(infos[i].g, &sy, &sz)) return false;
+  }
+  return true;
+}
+
+MultiCfg multi_cfg(int n, const OpInfo* infos) {
+  std::lock_guard<std::mutex> lk(g_multi_mu);
+  auto it = g_multi_cfg.find(multi_key(n, infos));
+  if (it != g_multi_cfg.end()) return it->second;
+  if (multi_stream_possible(n, infos)) return MultiCfg{1, 4, 1};
+  return MultiCfg{0, 1, 0};
+}
+
+// Validated lattice set of a multi-lattice call.
+int multi_check(int32_t n, const dirac_op* ops, const void* const* U, const void* const* psi, void* const* chi,
+                std::vector<OpInfo>& infos) {
   if (n < 1 || n > 8) return set_error(DIRAC_EINVAL, "dirac_multi_apply: n must be in 1..8");
   if (!ops || !U || !psi || !chi) return set_error(DIRAC_EINVAL, "dirac_multi_apply: NULL array");
-  std::vector<OpInfo> infos(n);
+  infos.resize(n);
   for (int k = 0; k < n; ++k) {
     CHECK(check_op(&ops[k], &infos[k], "dirac_multi_apply"));
     if (infos[k].nrhs != 1) return set_error(DIRAC_EINVAL, "dirac_multi_apply: nrhs must be 1");
@@ -487,7 +516,17 @@ int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U, cons
     if (overlap(psi[k], infos[k].field_bytes, chi[k], infos[k].field_bytes))
       return set_error(DIRAC_EINVAL, "dirac_multi_apply: output overlaps input");
   }
-  return multi_apply(n, infos.data(), U, psi, chi, dagger ? 1 : 0, (hipStream_t)stream);
+  return DIRAC_OK;
+}
+}  // namespace
+
+int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U, const void* const* psi,
+                      void* const* chi, int32_t dagger, void* stream) {
+  clear_error();
+  std::vector<OpInfo> infos;
+  CHECK(multi_check(n, ops, U, psi, chi, infos));
+  return multi_apply(n, infos.data(), U, psi, chi, dagger ? 1 : 0, multi_cfg(n, infos.data()),
+                     (hipStream_t)stream);
 }
 
 // --------------------------------------------------------- graph plans ----
@@ -501,6 +540,44 @@ int dirac_multi_plan_create(int32_t n, const dirac_op* ops, const void* const* U
   clear_error();
   if (plan_out == nullptr) return set_error(DIRAC_EINVAL, "dirac_multi_plan_create: plan_out is NULL");
   *plan_out = nullptr;
+  std::vector<OpInfo> infos;
+  CHECK(multi_check(n, ops, U, psi, chi, infos));
+  // time the launch forms on the caller's buffers and stream (chi is
+  // overwritten), remember the fastest for this set, then capture it
+  {
+    hipStream_t ts = (hipStream_t)stream;
+    std::vector<MultiCfg> cands{MultiCfg{0, 1, 0}};
+    if (multi_stream_possible(n, infos.data()))
+      for (int tc : {1, 2, 4, 8, 16})
+        for (int xcd : {0, 1}) cands.push_back(MultiCfg{1, tc, xcd});
+    hipEvent_t e0, e1;
+    CHECK(hip_status(hipEventCreate(&e0), "event"));
+    CHECK(hip_status(hipEventCreate(&e1), "event"));
+    MultiCfg best = cands[0];
+    float best_ms = 1e30f;
+    int rc = DIRAC_OK;
+    for (const MultiCfg& c : cands) {
+      for (int k = 0; k < 2 && rc == DIRAC_OK; ++k)
+        rc = multi_apply(n, infos.data(), U, psi, chi, dagger ? 1 : 0, c, ts);
+      if (rc == DIRAC_OK) rc = hip_status(hipEventRecord(e0, ts), "event record");
+      for (int k = 0; k < 10 && rc == DIRAC_OK; ++k)
+        rc = multi_apply(n, infos.data(), U, psi, chi, dagger ? 1 : 0, c, ts);
+      if (rc == DIRAC_OK) rc = hip_status(hipEventRecord(e1, ts), "event record");
+      if (rc == DIRAC_OK) rc = hip_status(hipEventSynchronize(e1), "event sync");
+      if (rc != DIRAC_OK) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DIRAC_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    g_multi_cfg[multi_key(n, infos.data())] = best;
+  }
   hipStream_t cap;
   CHECK(hip_status(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "plan stream"));
   int rc = hip_status(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -523,7 +600,6 @@ int dirac_multi_plan_create(int32_t n, const dirac_op* ops, const void* const* U
     }
   }
   (void)hipStreamDestroy(cap);
-  (void)stream;
   return rc;
 }
 
@@ -545,22 +621,21 @@ int dirac_plan_destroy(void* plan) {
 }
 
 // ------------------------------------------------------------ tuning -----
-// Streaming-kernel tiles worth timing for this geometry: all of x, tile_y x
-// tile_z chosen so the tile has 128 or 256 columns.
+// Streaming-kernel tiles worth timing for this geometry: all of x times
+// tile_y x tile_z with tile_y | Ly, tile_z | Lz, filling at least 3/4 of a
+// block of 128 or 256 threads.
 static std::vector<LaunchCfg> stream_candidates(const OpInfo& o) {
   std::vector<LaunchCfg> v;
-  if (o.nrhs != 1) return v;
-  for (int cols : {128, 256}) {
-    if (cols % o.g.X) continue;
-    const int yz = cols / o.g.X;
-    for (int sy = 1; sy <= yz; sy *= 2) {
-      const int sz = yz / sy;
-      if (sy * sz != yz) continue;
+  for (int sy = 1; sy <= o.g.Y; ++sy) {
+    if (o.g.Y % sy) continue;
+    for (int sz = 1; sz <= o.g.Z; ++sz) {
+      if (o.g.Z % sz) continue;
+      const int n = stream_columns(o.g, sy, sz);
+      if (n > 256 || 4 * n < 3 * stream_block(o.g, sy, sz)) continue;
       for (int tc : {1, 2, 4, 8, 16}) {
         if (tc > o.g.T) continue;
         if (!stream_fits(o.g, sy, sz, tc)) continue;
-        LaunchCfg c{64, 1, 1, 1, 0, sy, sz, tc, 1};
-        v.push_back(c);
+        v.push_back(LaunchCfg{64, 1, 1, 1, 0, sy, sz, tc, 1});
       }
     }
   }
@@ -663,11 +738,10 @@ int dirac_set_launch_config(const dirac_op* op, const dirac_launch* cfg) {
     if (cfg->xcd_remap < 0 || cfg->xcd_remap > 7)
       return set_error(DIRAC_EINVAL, "dirac_set_launch_config: xcd_remap of the streaming kernel is a 3-bit mask");
     c.remap = cfg->xcd_remap;
-    if (o.nrhs != 1) return set_error(DIRAC_EINVAL, "dirac_set_launch_config: the streaming kernel takes nrhs = 1");
     if (!stream_fits(o.g, c.sy, c.sz, c.tc))
       return set_error(DIRAC_EINVAL,
                        "dirac_set_launch_config: tile %d x %d x %d (x, y, z) must divide the lattice and have "
-                       "128 or 256 columns, t_chunk >= 1",
+                       "32 to 256 columns, t_chunk >= 1",
                        o.g.X, c.sy, c.sz);
     c.S = 64;
     c.R = 1;

@@ -90,8 +90,8 @@ constexpr int kStreamAlt = 4;   // odd t-chunks walk downwards
 // in opposite directions read their shared halo slice and link at the same
 // time (both at the start, or both at the end of the walk).
 template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN>
-__device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, int z, int yl, int zl, int t0,
-                                            int t1, char* lds_raw, double& val) {
+__device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool act, int x, int y, int z, int yl,
+                                            int zl, int t0, int t1, char* lds_raw, double& val) {
   using SI = SpinFmt<PI>;
   using SO = SpinFmt<PO>;
   using LF = LinkFmt<PI, LK>;
@@ -104,7 +104,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, i
   const int BY = a.sy, BZ = a.sz;
   const int tid = threadIdx.x;
   const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
-  const Rsrc in = make_rsrc(a.in, a.field_bytes);
+  const Rsrc in = make_rsrc(a.in + (size_t)rhs * a.in_stride, a.field_bytes);
   const int xp = (x + 1 == g.X) ? 0 : x + 1, xm = (x == 0) ? g.X - 1 : x - 1;
   const int yp = (y + 1 == g.Y) ? 0 : y + 1, ym = (y == 0) ? g.Y - 1 : y - 1;
   const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, i
   // prologue: centre psi(ts) into buffer 0 and the hop carried into ts from
   // the slice before it in walking order, kept as w = U^(dag) h (12 reals)
   Cx<Rl> Wt[2][3];
-  {
+  if (act) {
     int p, i;
     site_pi(g, x, y, z, ts, p, i);
     Cx<Rl> v[12];
@@ -154,6 +154,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, i
     const int b = s & 1;
     const StreamLds<PI, NC> cur_s{lbase + b * 12 * NC};        // slice t
     const StreamLds<PI, NC> nxt_s{lbase + (b ^ 1) * 12 * NC};  // slice tn
+    if (act) {
     int p, i;
     site_pi(g, x, y, z, t, p, i);
     const int tn = DOWN ? ((t == 0) ? g.T - 1 : t - 1) : ((t + 1 == g.T) ? 0 : t + 1);
@@ -256,7 +257,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, i
 #pragma unroll
     for (int k = 0; k < 12; ++k)
       o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
-    const Rsrc orsrc = make_rsrc(a.out, a.out_bytes);
+    const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
     if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
       if (a.nt_store)
         SO::template store<2>(orsrc, Vh, p, i, o);
@@ -273,9 +274,9 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, i
         val += sum;
       }
     } else {
-      const Ro cf = a.sub_alpha ? (Ro)a.red.state[0].alpha : Ro(1);
+      const Ro cf = a.sub_alpha ? (Ro)a.red.state[rhs].alpha : Ro(1);
       Cx<Ro> d[12];
-      SO::load(make_rsrc(a.src, a.out_bytes), Vh, p, i, d);
+      SO::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
       double sum = 0.0;
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
@@ -286,6 +287,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int x, int y, i
       SO::template store<0>(orsrc, Vh, p, i, d);
       val += sum;
     }
+    }  // act
     __syncthreads();  // slice tn complete; slice t no longer read
   }
 }
@@ -298,13 +300,18 @@ k_dslash_stream(DslashArgs a) {
   const Geom g = a.g;
   const int BY = a.sy, BZ = a.sz;
   const int tid = threadIdx.x;
+  // threads past the tile's X * BY * BZ columns only take part in barriers
+  const bool act = tid < g.X * BY * BZ;
   const int x = tid % g.X;
   const int yl = (tid / g.X) % BY;
   const int zl = tid / (g.X * BY);
   const int nty = g.Y / BY, ntz = g.Z / BZ;
-  const int nblocks = a.ntiles;
-  const int ntt = nblocks / (nty * ntz);
-  const int l = xcd_tile(blockIdx.x, nblocks, a.remap & kStreamXcd);
+  const int ntt = a.ntiles / (nty * ntz);
+  // blocks = tiles x right-hand sides, the right-hand side fastest: the
+  // blocks of one tile run side by side and share its link loads in the L2
+  const int lb = xcd_tile(blockIdx.x, a.ntiles * a.nrhs, a.remap & kStreamXcd);
+  const int rhs = lb % a.nrhs;
+  const int l = lb / a.nrhs;
   int ty, tz, tt;
   if (a.remap & kStreamTFast) {
     tt = l % ntt;
@@ -320,41 +327,46 @@ k_dslash_stream(DslashArgs a) {
   const int t1 = min(t0 + a.tc, g.T);
 
   bool on = true;
-  if (a.gate == kGateNotDone) on = !a.red.state[0].done;
-  if (a.gate == kGateActive) on = a.red.state[0].active != 0;
+  if (a.gate == kGateNotDone) on = !a.red.state[rhs].done;
+  if (a.gate == kGateActive) on = a.red.state[rhs].active != 0;
   double vals[1][1] = {{0.0}};
   if (on) {
     if ((a.remap & kStreamAlt) && (tt & 1))
-      stream_walk<PI, PO, LK, DAG, EPI, NC, true>(a, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+      stream_walk<PI, PO, LK, DAG, EPI, NC, true>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
     else
-      stream_walk<PI, PO, LK, DAG, EPI, NC, false>(a, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+      stream_walk<PI, PO, LK, DAG, EPI, NC, false>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
   }
-  if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, 0, 1, blockIdx.x, nblocks);
+  if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, l, a.ntiles);
 }
 
-// Tile/geometry check of the streaming kernel (host).
+// Tile/geometry check of the streaming kernel (host): the tile's y and z
+// extents divide the lattice's, and its X * tile_y * tile_z columns fit a
+// block of 128 or 256 threads (32 to 256 columns; spare threads idle).
+inline int stream_columns(const Geom& g, int sy, int sz) { return g.X * sy * sz; }
+inline int stream_block(const Geom& g, int sy, int sz) { return stream_columns(g, sy, sz) <= 128 ? 128 : 256; }
 inline bool stream_fits(const Geom& g, int sy, int sz, int tc) {
   if (sy < 1 || sz < 1 || tc < 1) return false;
   if (g.Y % sy || g.Z % sz) return false;
-  const int n = g.X * sy * sz;
-  return n == 128 || n == 256;
+  const int n = stream_columns(g, sy, sz);
+  return n >= 32 && n <= 256;
 }
 
 template <int PI, int PO, int LK, bool DAG, int EPI>
 hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
-  if (!stream_fits(a.g, a.sy, a.sz, a.tc) || a.nrhs != 1) return hipErrorInvalidValue;
+  if (!stream_fits(a.g, a.sy, a.sz, a.tc) || a.nrhs < 1) return hipErrorInvalidValue;
   const int nty = a.g.Y / a.sy, ntz = a.g.Z / a.sz, ntt = (a.g.T + a.tc - 1) / a.tc;
   a.ntiles = nty * ntz * ntt;
   a.ngroups = 1;
-  const int ncols = a.g.X * a.sy * a.sz;
-  const size_t lds = (size_t)ncols * (PI == DIRAC_F64 ? 30 : 24) * sizeof(Cx<typename SpinFmt<PI>::R>);
-  if (ncols == 256)
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), dim3(a.ntiles), dim3(256), lds, st, a);
+  const int nc = stream_block(a.g, a.sy, a.sz);
+  const size_t lds = (size_t)nc * (PI == DIRAC_F64 ? 30 : 24) * sizeof(Cx<typename SpinFmt<PI>::R>);
+  const dim3 grid(a.ntiles * a.nrhs);
+  if (nc == 256)
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), grid, dim3(256), lds, st, a);
   else
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128>), dim3(a.ntiles), dim3(128), lds, st, a);
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128>), grid, dim3(128), lds, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || EPI == kEpiStore) return e;
-  return launch_finalize(a.red, a.ntiles, 1, 1, st);
+  return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);
 }
 
 #define DIRAC_DSLASH_STREAM_ENTRY(PI, PO, LK, DAG, EPI) \

@@ -62,8 +62,15 @@ struct Scratch {
 };
 int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out);
 
-// Multi-lattice persistent launch (multi.hip).
+// Multi-lattice persistent launch (multi.hip): per-site form, or t-streaming
+// tiles with a common t_chunk (optionally dealt to XCDs in contiguous runs).
+struct MultiCfg {
+  int stream;
+  int tc;
+  int xcd;
+};
+bool multi_stream_tile(const Geom& g, int* sy, int* sz);
 int multi_apply(int n, const OpInfo* infos, const void* const* U, const void* const* psi, void* const* chi,
-                int dagger, hipStream_t st);
+                int dagger, const MultiCfg& cfg, hipStream_t st);
 
 }  // namespace dirac

@@ -119,13 +119,16 @@ def test_launch_config_validation():
     L = abi.DiracLaunch
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(96, 1, 1, 0, 0, 1, 1, 1, 0))) == abi.EINVAL
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(128, 5, 1, 0, 0, 1, 1, 1, 0))) == abi.EINVAL
-    # streaming tiles must divide the lattice and have 128 or 256 columns
+    # streaming tiles must divide the lattice and have 32 to 256 columns
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 3, 1, 1, 0))) == abi.EINVAL
-    assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 1, 1, 2, 0))) == abi.EINVAL
+    op16 = _op(dims=(16, 16, 16, 16))
+    assert lib.dirac_set_launch_config(C.byref(op16), C.byref(L(64, 1, 1, 0, 1, 8, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
     op8 = _op(dims=(8, 4, 4, 4))
     assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
     assert lib.dirac_set_launch_config(C.byref(_op(dims=(8, 4, 4, 4), nrhs=2)),
-                                       C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+                                       C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
     got = abi.DiracLaunch()
     assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
     assert (got.lds, got.tile_y, got.tile_z, got.t_chunk, got.tuned) == (1, 4, 4, 2, 1)

@@ -167,6 +167,23 @@ def test_batched_rhs_match_single(inner):
         assert rel_2(xb[k], xs) <= freefield.condition_number(m) * 2e-10
 
 
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
+def test_batched_cg_with_stream_kernels(inner):
+    # per-RHS gates, alpha and norm partials of the streaming kernel
+    dims = (8, 4, 4, 8)
+    g = synth.rng(13)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)[:4] + 0.1 * synth.spinor_gauss(dims, g, nrhs=4)
+    src[2] *= 1e-3  # convergence is relative to each source's own norm
+    m = 0.1
+    for prec in ("f64", "f32", "f16s"):
+        D.Operator(dims, m, prec, 12, 4).set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=3, xcd_remap=7)
+    xb, stb = solve(U, src, m, link=12, inner=inner, nrhs=4)
+    for k in range(4):
+        assert stb[k]["status"] == abi.OK
+        assert true_res(U, src[k], xb[k], m) < 1e-10
+
+
 def test_failure_paths_and_resume():
     dims = (4, 4, 4, 4)
     U, eta = inputs(dims, "haar", seed=6)

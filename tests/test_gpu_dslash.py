@@ -113,6 +113,30 @@ def test_multi_rhs_point_sources(prec):
     assert rel_inf(got, ref) <= (5e-6 if prec == "f32" else 1.5e-3)
 
 
+@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
+                                           ("f16s", 12, 1.5e-3)])
+@pytest.mark.parametrize("remap", [1, 7])
+def test_stream_multi_rhs(prec, link, tol, remap):
+    # one streaming block per (tile, rhs): each column equals the oracle and,
+    # bit for bit, the single-RHS streaming launch of the same source
+    dims = (8, 8, 4, 6)
+    g = synth.rng(12)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)[:5] + 0.2 * synth.spinor_gauss(dims, g, nrhs=5)
+    m = 0.07
+    op = D.Operator(dims, m, prec, link, 5)
+    op.set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=4, xcd_remap=remap, nt_store=1)
+    Ui = op.pack_gauge(cuda(U))
+    got = host(op.unpack_spinor(op.apply(Ui, op.pack_spinor(cuda(src)))))
+    one = D.Operator(dims, m, prec, link, 1)
+    one.set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=4, xcd_remap=remap, nt_store=1)
+    for k in range(5):
+        ref = wilson.dslash(lowprec.store_links(U, prec), lowprec.store(src[k], prec), m)
+        assert rel_inf(got[k], ref) <= tol, k
+        single = host(one.unpack_spinor(one.apply(Ui, one.pack_spinor(cuda(src[k])))))
+        assert np.array_equal(got[k], single), k
+
+
 def test_pack_roundtrips():
     dims = (4, 2, 6, 2)
     U, psi = inputs(dims, "haar", seed=6)
@@ -187,7 +211,12 @@ def test_split_kernel_parity(prec, link, tol, dagger):
 
 
 STREAM_CASES = [
-    # dims, (tile_y, tile_z), t_chunk    (tile = all of x times tile_y times tile_z: 128 or 256 columns)
+    # dims, (tile_y, tile_z), t_chunk    (tile = all of x times tile_y times tile_z: 32 to 256
+    # columns in a block of 128 or 256 threads; spare threads idle)
+    ((12, 6, 4, 6), (2, 2), 2),    # 48 of 128 threads
+    ((24, 4, 6, 4), (2, 3), 3),    # 144 of 256 threads, ragged chunk
+    ((6, 4, 4, 4), (4, 4), 1),     # 96 columns, one tile spans y and z
+    ((2, 4, 4, 4), (4, 4), 2),     # X = 2: both x hops reach the same neighbour
     ((8, 4, 4, 8), (4, 4), 1),
     ((8, 4, 4, 8), (4, 4), 3),     # ragged last chunk
     ((16, 8, 8, 6), (4, 2), 4),    # faces in y and z

@@ -33,10 +33,15 @@ def _setup(dims_list, masses, prec, link):
     return ops, Us, ps, cs, raw
 
 
-@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f32", 12, 5e-6)])
+@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f32", 12, 5e-6), ("f16s", 12, 1.5e-3)])
 @pytest.mark.parametrize("dagger", [False, True])
-def test_multi_small_uneven(prec, link, tol, dagger):
-    dims_list = [(4, 4, 4, 4), (6, 2, 4, 8), (2, 2, 2, 2), (8, 6, 4, 2)]
+@pytest.mark.parametrize("dims_list", [
+    # 2^4 has no streaming tile (8 columns): the per-site form
+    [(4, 4, 4, 4), (6, 2, 4, 8), (2, 2, 2, 2), (8, 6, 4, 2)],
+    # every lattice has a streaming tile (64, 48, 192, 144 columns)
+    [(4, 4, 4, 4), (6, 2, 4, 8), (8, 6, 4, 2), (12, 4, 6, 6)],
+])
+def test_multi_small_uneven(prec, link, tol, dagger, dims_list):
     masses = [0.02, 0.08, 0.14, 0.2]
     ops, Us, ps, cs, raw = _setup(dims_list, masses, prec, link)
     D.multi_apply(ops, Us, ps, cs, dagger=dagger)
@@ -63,7 +68,12 @@ def test_multi_c4_set_and_graph_replay():
         got = host(op.unpack_spinor(c))[s[:, 3], s[:, 2], s[:, 1], s[:, 0]]
         assert rel_inf(got, ref) <= 5e-6
     # graph replay: several replays with eager work in between, each checked
+    # bitwise against an eager call in the launch form the plan chose
     plan = D.MultiPlan(ops, Us, ps, cs)
+    D.multi_apply(ops, Us, ps, cs)
+    first = [host(op.unpack_spinor(c)) for op, c in zip(ops, cs)]
+    for f, r in zip(first, refs):
+        assert rel_inf(f, r) <= 1e-6
     try:
         for rep in range(3):
             for c in cs:
