@@ -65,6 +65,13 @@ def kernel_name(prec, link, cfg, dims, dagger=False):
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_f64_16x16x16x32_traffic.json")
 
+# Streaming launches of the headline timed on rotated inputs beside the
+# autotuner's pick (tile_y x tile_z, t_chunk 2; the fastest cold in sweeps).
+HEADLINE_CANDIDATES = [
+    dict(block_sites=64, rhs_per_thread=1, xcd_remap=r, nt_store=1, lds=1, tile_y=ty, tile_z=tz, t_chunk=2)
+    for (ty, tz, r) in ((4, 4, 7), (8, 2, 1), (16, 1, 1), (4, 4, 1), (8, 2, 7))
+]
+
 
 def profiled_record():
     """The committed FETCH_SIZE / WRITE_SIZE record of the headline kernel, or
@@ -116,14 +123,30 @@ class Timer:
         self.ms = self.a.elapsed_time(self.b)
 
 
+def _set_launch(op, launch):
+    op.set_launch_config(**{k: v for k, v in launch.items() if k != "tuned"})
+
+
+def _rotated_ms(torch, op, sets, steps, dagger=False):
+    with Timer(torch) as t:
+        for k in range(steps):
+            u, p, c = sets[k % len(sets)]
+            op.apply(u, p, out=c, dagger=dagger)
+    return t.ms / steps
+
+
 def time_dslash(torch, D, dims, prec, link, U, psi, steps, warmup, nrhs=1, m_q=0.05, dagger=False,
-                tune=True, launch=None, force_tune=False):
+                tune=True, launch=None, force_tune=False, cold_candidates=()):
     """Average ms of one D application, rotating over enough input copies to
     defeat the last-level cache.  ``launch`` fixes the launch configuration,
-    else the autotuner picks it.  Returns (ms, copies, launch config)."""
+    else the autotuner picks it; the autotuner times candidates on one
+    (cache-resident) input set, so ``cold_candidates`` lists further launch
+    configurations that are timed together with its pick on the rotated
+    inputs, and the fastest of them is used.  Returns (ms, copies, launch
+    config)."""
     op = D.Operator(dims, m_q, prec, link, nrhs)
     if launch is not None:
-        op.set_launch_config(**{k: v for k, v in launch.items() if k != "tuned"})
+        _set_launch(op, launch)
         tune = False
     Ui = op.pack_gauge(torch.from_numpy(U).cuda())
     pi = op.pack_spinor(torch.from_numpy(psi).cuda())
@@ -134,14 +157,19 @@ def time_dslash(torch, D, dims, prec, link, U, psi, steps, warmup, nrhs=1, m_q=0
         sets.append((Ui.clone(), pi.clone(), op.empty_spinor()))
     if tune and (force_tune or not op.launch_config()["tuned"]):
         op.autotune(Ui, pi, sets[0][2])
+    if tune and cold_candidates:
+        best = None
+        for cand in [op.launch_config()] + list(cold_candidates):
+            _set_launch(op, cand)
+            _rotated_ms(torch, op, sets, 10, dagger)
+            ms = min(_rotated_ms(torch, op, sets, 100, dagger) for _ in range(2))
+            if best is None or ms < best[0]:
+                best = (ms, cand)
+        _set_launch(op, best[1])
     for k in range(warmup):
         u, p, c = sets[k % copies]
         op.apply(u, p, out=c, dagger=dagger)
-    with Timer(torch) as t:
-        for k in range(steps):
-            u, p, c = sets[k % copies]
-            op.apply(u, p, out=c, dagger=dagger)
-    return t.ms / steps, copies, op.launch_config()
+    return _rotated_ms(torch, op, sets, steps, dagger), copies, op.launch_config()
 
 
 def cg_time(torch, D, dims, U, eta, m_q, inner, link=18, tol=1e-10, reps=1):
@@ -380,6 +408,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the plain copy measured as the bandwidth ceiling (0: skip)")
+    ap.add_argument("--headline-launch", default=None,
+                    help="JSON launch configuration of the headline Dslash (no tuning); for profiling runs")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); "
@@ -403,8 +433,11 @@ def main(argv=None):
     # time describe the same kernel; the autotuner's own pick is timed too.
     rec = profiled_record()
     fixed = rec["launch"] if rec is not None else None
+    if a.headline_launch:
+        fixed = json.loads(a.headline_launch)
     log("headline: float64 Dslash 16^3x32, 18-real links")
-    ms, copies, cfg = time_dslash(torch, D, dims, "f64", 18, U, psi, a.steps, a.warmup, m_q=m_q, launch=fixed)
+    ms, copies, cfg = time_dslash(torch, D, dims, "f64", 18, U, psi, a.steps, a.warmup, m_q=m_q, launch=fixed,
+                                  cold_candidates=HEADLINE_CANDIDATES)
     tuned = None
     if fixed is not None and not a.quick:
         ms_t, _, cfg_t = time_dslash(torch, D, dims, "f64", 18, U, psi, a.steps, a.warmup, m_q=m_q,
