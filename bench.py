@@ -172,14 +172,24 @@ def time_dslash(torch, D, dims, prec, link, U, psi, steps, warmup, nrhs=1, m_q=0
     return _rotated_ms(torch, op, sets, steps, dagger), copies, op.launch_config()
 
 
+def tune_for_solve(op, U_int, src_int):
+    """Autotune ``op`` (if not done yet) on a source of its precision.  CG
+    vectors are re-read every iteration, so the tuner's warm timing is the
+    regime a solve runs in."""
+    if not op.launch_config()["tuned"]:
+        op.autotune(U_int, src_int, op.empty_spinor())
+
+
 def cg_time(torch, D, dims, U, eta, m_q, inner, link=18, tol=1e-10, reps=1):
     op = D.Operator(dims, m_q, "f64", link)
     Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    e = op.pack_spinor(torch.from_numpy(eta).cuda())
+    tune_for_solve(op, Ui, e)
     Ul = None
     if inner != "f64":
         lo = op.like(prec=inner, link=link if inner == "f32" else 12)
         Ul = lo.pack_gauge(torch.from_numpy(U).cuda())
-    e = op.pack_spinor(torch.from_numpy(eta).cuda())
+        tune_for_solve(lo, Ul, lo.pack_spinor(torch.from_numpy(eta).cuda()))
     # one untimed solve (tuning, first-touch), then the timed ones
     D.cg(op, Ui, e, tol=tol, inner_prec=inner, U_lo=Ul)
     best = None
@@ -199,11 +209,13 @@ def cg_time_multi(torch, D, dims, U, src, m_q, inner, link=12, tol=1e-10):
     nrhs = src.shape[0]
     op = D.Operator(dims, m_q, "f64", link, nrhs)
     Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    e = op.pack_spinor(torch.from_numpy(src).cuda())
+    tune_for_solve(op, Ui, e)
     Ul = None
     if inner != "f64":
-        Ul = op.like(prec=inner, link=link if inner == "f32" else 12, nrhs=nrhs).pack_gauge(
-            torch.from_numpy(U).cuda())
-    e = op.pack_spinor(torch.from_numpy(src).cuda())
+        lo = op.like(prec=inner, link=link if inner == "f32" else 12, nrhs=nrhs)
+        Ul = lo.pack_gauge(torch.from_numpy(U).cuda())
+        tune_for_solve(lo, Ul, lo.pack_spinor(torch.from_numpy(src).cuda()))
     D.cg(op, Ui, e, tol=tol, inner_prec=inner, U_lo=Ul)  # untimed: tuning, first touch
     x = torch.zeros_like(e)
     with Timer(torch) as t:

@@ -189,6 +189,10 @@ void load_cache_file_locked() {
   std::fclose(f);
 }
 
+// Untuned default: the t-streaming kernel on the largest (then squarest)
+// tile of at most 256 columns, with the largest t_chunk up to 16 that still
+// gives about four blocks per CU (never below 2), the alternating walk and
+// the XCD order; the per-site kernel where no streaming tile fits.
 LaunchCfg default_cfg(const OpInfo& o) {
   LaunchCfg c;
   c.S = 256;
@@ -201,6 +205,17 @@ LaunchCfg default_cfg(const OpInfo& o) {
     c.R = 1;
   else
     c.R = std::min(o.nrhs, o.prec == DIRAC_F64 ? 2 : 3);
+  int sy, sz;
+  if (multi_stream_tile(o.g, &sy, &sz)) {
+    const int64_t yz = (int64_t)(o.g.Y / sy) * (o.g.Z / sz) * o.nrhs;
+    int tc = 2;
+    for (int t : {16, 8, 4, 2})
+      if (t <= o.g.T && yz * ((o.g.T + t - 1) / t) >= 1024) {
+        tc = t;
+        break;
+      }
+    c = LaunchCfg{64, 1, 1 | 4, 1, 1, sy, sz, std::min(tc, o.g.T), 0};
+  }
   return c;
 }
 }  // namespace
