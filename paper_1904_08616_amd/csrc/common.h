@@ -181,6 +181,10 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Offset of parity plane p (0 or 1) when one plane is `plane` bytes: a
+// select, not an integer multiply (a quarter-rate instruction).
+__device__ __forceinline__ uint32_t plane_off(int p, uint32_t plane) { return p ? plane : 0u; }
+
 template <class T>
 __device__ __forceinline__ T bld(Rsrc r, uint32_t voff, uint32_t soff) {
   static_assert(sizeof(T) == 16 || sizeof(T) == 8 || sizeof(T) == 4, "buffer load size");
@@ -219,7 +223,7 @@ template <> struct SpinFmt<DIRAC_F64> {
   static constexpr bool kScaled = false;
   static constexpr int kSiteBytes = 192;
   __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 12u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       double2 t = bld<double2>(f, o, (uint32_t)c * (uint32_t)Vh * 16u);
@@ -229,7 +233,7 @@ template <> struct SpinFmt<DIRAC_F64> {
   __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
   template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 12u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int c = 0; c < 12; ++c)
       bst<AUX>(f, o, (uint32_t)c * (uint32_t)Vh * 16u, make_double2(v[c].re, v[c].im));
@@ -238,7 +242,7 @@ template <> struct SpinFmt<DIRAC_F64> {
   template <int AUX = 0>
   __device__ static __forceinline__ void store_range(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
                                                      int v0, int v1) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 12u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int c = 0; c < 12; ++c)
       if (c >= v0 && c < v1)
@@ -247,7 +251,7 @@ template <> struct SpinFmt<DIRAC_F64> {
   // Load only the storage vectors [v0, v1); other components are zero.
   __device__ static __forceinline__ void load_range(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12], int v0,
                                                     int v1) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 12) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 12u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
       v[c] = {0.0, 0.0};
@@ -265,7 +269,7 @@ template <> struct SpinFmt<DIRAC_F32> {
   static constexpr bool kScaled = false;
   static constexpr int kSiteBytes = 96;
   __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 6u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       float4 t = bld<float4>(f, o, (uint32_t)k * (uint32_t)Vh * 16u);
@@ -276,7 +280,7 @@ template <> struct SpinFmt<DIRAC_F32> {
   __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
   template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 6u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
       bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u,
@@ -285,7 +289,7 @@ template <> struct SpinFmt<DIRAC_F32> {
   // Load only the storage vectors [v0, v1); other components are zero.
   __device__ static __forceinline__ void load_range(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12], int v0,
                                                     int v1) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 6u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       v[2 * k] = {0.f, 0.f};
@@ -301,7 +305,7 @@ template <> struct SpinFmt<DIRAC_F32> {
   template <int AUX = 0>
   __device__ static __forceinline__ void store_range(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
                                                      int v0, int v1) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 6) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 6u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
       if (k >= v0 && k < v1)
@@ -319,10 +323,10 @@ template <bool BF> struct SpinScaled {
   __device__ static __forceinline__ unsigned short enc(float f) { return BF ? f_to_bf16(f) : f_to_h(f); }
   // the scales follow the 2 * Vh * 48 payload bytes
   __device__ static __forceinline__ uint32_t scale_off(int Vh, int p) {
-    return (uint32_t)Vh * 96u + (uint32_t)p * (uint32_t)Vh * 4u;
+    return (uint32_t)Vh * 96u + plane_off(p, (uint32_t)Vh * 4u);
   }
   __device__ static __forceinline__ void load(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12]) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 3u * (uint32_t)Vh * 16u);
     const float s = bld<float>(f, (uint32_t)i * 4u + scale_off(Vh, p), 0u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -333,31 +337,38 @@ template <bool BF> struct SpinScaled {
         v[4 * k + j] = {s * dec((unsigned short)(w[j] & 0xFFFFu)), s * dec((unsigned short)(w[j] >> 16))};
     }
   }
-  // Replace v by the value the store would leave in memory.
-  __device__ static __forceinline__ void round(Cx<R> (&v)[12]) {
+  // Site maximum |v| and its reciprocal (0 for an all-zero site).  The
+  // quotients are formed as v * (1/m): within one float ulp of v / m, and
+  // the site maximum still rounds to exactly +-1 in the 16-bit format; one
+  // division per site instead of 24.
+  __device__ static __forceinline__ float site_max(const Cx<R> (&v)[12]) {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    return m;
+  }
+  // Replace v by the value the store would leave in memory.
+  __device__ static __forceinline__ void round(Cx<R> (&v)[12]) {
+    const float m = site_max(v);
+    const float inv = (m > 0.f) ? 1.f / m : 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      v[c].re = (m > 0.f) ? m * dec(enc(v[c].re / m)) : 0.f;
-      v[c].im = (m > 0.f) ? m * dec(enc(v[c].im / m)) : 0.f;
+      v[c].re = m * dec(enc(v[c].re * inv));
+      v[c].im = m * dec(enc(v[c].im * inv));
     }
   }
   template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
-    float m = 0.f;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 3) * (uint32_t)Vh * 16u;
+    const float m = site_max(v);
+    const float inv = (m > 0.f) ? 1.f / m : 0.f;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 3u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       unsigned w[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        // divide (not multiply by 1/m) so the site maximum maps to +-1 exactly
-        float re = (m > 0.f) ? v[4 * k + j].re / m : 0.f;
-        float im = (m > 0.f) ? v[4 * k + j].im / m : 0.f;
+        const float re = v[4 * k + j].re * inv;
+        const float im = v[4 * k + j].im * inv;
         w[j] = (unsigned)enc(re) | ((unsigned)enc(im) << 16);
       }
       bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));
@@ -389,7 +400,7 @@ template <int LK> struct LinkF64 {
   static constexpr int NL = LK / 2;
   static constexpr int kBytes = LK * 8;
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 4 * NL) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 4u * NL * (uint32_t)Vh * 16u);
     const uint32_t base = (uint32_t)(mu * NL) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
@@ -407,7 +418,7 @@ template <> struct LinkFmt<DIRAC_F32, 18> {
   static constexpr int NL = 9;
   static constexpr int kBytes = 72;
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 8u + (uint32_t)(p * 4 * 9) * (uint32_t)Vh * 8u;
+    const uint32_t o = (uint32_t)i * 8u + plane_off(p, 4u * 9u * (uint32_t)Vh * 8u);
     const uint32_t base = (uint32_t)(mu * 9) * (uint32_t)Vh * 8u;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -421,7 +432,7 @@ template <> struct LinkFmt<DIRAC_F32, 12> {
   static constexpr int NL = 3;
   static constexpr int kBytes = 48;
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 16u + (uint32_t)(p * 4 * 3) * (uint32_t)Vh * 16u;
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 4u * 3u * (uint32_t)Vh * 16u);
     const uint32_t base = (uint32_t)(mu * 3) * (uint32_t)Vh * 16u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -438,7 +449,7 @@ template <bool BF> struct LinkHalf12 {
   static constexpr int kBytes = 24;
   __device__ static __forceinline__ float dec(unsigned short h) { return BF ? bf16_to_f(h) : h_to_f(h); }
   __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
-    const uint32_t o = (uint32_t)i * 8u + (uint32_t)(p * 4 * 3) * (uint32_t)Vh * 8u;
+    const uint32_t o = (uint32_t)i * 8u + plane_off(p, 4u * 3u * (uint32_t)Vh * 8u);
     const uint32_t base = (uint32_t)(mu * 3) * (uint32_t)Vh * 8u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {

@@ -48,12 +48,6 @@ __device__ __forceinline__ void pin12(Cx<R> (&acc)[12]) {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Lexicographic parity and checkerboard index of (x, y, z, t).
-__device__ __forceinline__ void site_pi(const Geom& g, int x, int y, int z, int t, int& p, int& i) {
-  p = (x + y + z + t) & 1;
-  i = (((t * g.Z + z) * g.Y + y) * g.X + x) >> 1;
-}
-
 // One hop of eq. (1) from an already loaded neighbour spinor v:
 // FWD: acc += U (1 - S gamma_mu) v;  backward: acc += U^dag (1 + S gamma_mu) v.
 template <int MU, bool DAG, bool FWD, class R>
@@ -110,6 +104,20 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
   const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
   const int col_xp = tid - x + xp, col_xm = tid - x + xm;
   const bool in_yp = yl + 1 < BY, in_ym = yl > 0, in_zp = zl + 1 < BZ, in_zm = zl > 0;
+  // Lexicographic offsets of this thread's (x, y, z) column and of its
+  // spatial neighbours within one time slice; a site's index is then
+  // (t * X*Y*Z + column) / 2, with t uniform over the block.  Every +-1
+  // neighbour has the other parity (all extents are even).
+  const int cpar = (x + y + z) & 1;
+  const int ccol = (z * g.Y + y) * g.X + x;
+  const int ccol_xm = ccol - x + xm;
+  const int ccol_yp = ccol + (yp - y) * g.X, ccol_ym = ccol + (ym - y) * g.X;
+  const int ccol_zp = ccol + (zp - z) * g.X * g.Y, ccol_zm = ccol + (zm - z) * g.X * g.Y;
+  const int slice = g.X * g.Y * g.Z;
+  auto at = [&](int col, int par, int t, int& p, int& i) {
+    p = (par + t) & 1;
+    i = (t * slice + col) >> 1;
+  };
   // LDS: two slice buffers [2][12][NC] (slice t is read while the next one
   // is written) and, in float64, a private slot per thread for the carried hop.
   Cx<Rl>* const lbase = reinterpret_cast<Cx<Rl>*>(lds_raw);
@@ -123,13 +131,13 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
   Cx<Rl> Wt[2][3];
   if (act) {
     int p, i;
-    site_pi(g, x, y, z, ts, p, i);
+    at(ccol, cpar, ts, p, i);
     Cx<Rl> v[12];
     SI::load(in, Vh, p, i, v);
     StreamLds<PI, NC>{lbase}.put(tid, v);
     const int tq = DOWN ? ((ts + 1 == g.T) ? 0 : ts + 1) : ((ts == 0) ? g.T - 1 : ts - 1);
     int pq, iq;
-    site_pi(g, x, y, z, tq, pq, iq);
+    at(ccol, cpar, tq, pq, iq);
     SI::load(in, Vh, pq, iq, v);
     M3<Rl> u;
     Cx<Rl> h[2][3];
@@ -156,10 +164,10 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
     const StreamLds<PI, NC> nxt_s{lbase + (b ^ 1) * 12 * NC};  // slice tn
     if (act) {
     int p, i;
-    site_pi(g, x, y, z, t, p, i);
+    at(ccol, cpar, t, p, i);
     const int tn = DOWN ? ((t == 0) ? g.T - 1 : t - 1) : ((t + 1 == g.T) ? 0 : t + 1);
     int pn, in_;
-    site_pi(g, x, y, z, tn, pn, in_);
+    at(ccol, cpar, tn, pn, in_);
     Cx<Rl> nxt[12];
     SI::load(in, Vh, pn, in_, nxt);
 
@@ -180,7 +188,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       hop_apply<0, DAG, true>(u, v, acc);
       {
         int pb, ib;
-        site_pi(g, xm, y, z, t, pb, ib);
+        at(ccol_xm, cpar ^ 1, t, pb, ib);
         LF::load(Ur, Vh, pb, 0, ib, u);
       }
       cur_s.get(col_xm, v);
@@ -193,13 +201,13 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         cur_s.get(tid + g.X, v);
       } else {
         int pf, jf;
-        site_pi(g, x, yp, z, t, pf, jf);
+        at(ccol_yp, cpar ^ 1, t, pf, jf);
         SI::load(in, Vh, pf, jf, v);
       }
       hop_apply<1, DAG, true>(u, v, acc);
       {
         int pb, ib;
-        site_pi(g, x, ym, z, t, pb, ib);
+        at(ccol_ym, cpar ^ 1, t, pb, ib);
         LF::load(Ur, Vh, pb, 1, ib, u);
         if (in_ym)
           cur_s.get(tid - g.X, v);
@@ -214,13 +222,13 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         cur_s.get(tid + g.X * BY, v);
       } else {
         int pf, jf;
-        site_pi(g, x, y, zp, t, pf, jf);
+        at(ccol_zp, cpar ^ 1, t, pf, jf);
         SI::load(in, Vh, pf, jf, v);
       }
       hop_apply<2, DAG, true>(u, v, acc);
       {
         int pb, ib;
-        site_pi(g, x, y, zm, t, pb, ib);
+        at(ccol_zm, cpar ^ 1, t, pb, ib);
         LF::load(Ur, Vh, pb, 2, ib, u);
         if (in_zm)
           cur_s.get(tid - g.X * BY, v);
