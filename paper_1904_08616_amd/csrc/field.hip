@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(Geom g, int nb, FieldDev f) {
 template <int MU, class R>
 __device__ __forceinline__ void force_dir(const Geom& g, const Rsrc& gr, const Rsrc& pr, int p, int i,
                                           const Coord& c, const Cx<R> (&gn)[12], const Cx<R> (&pn)[12],
-                                          double coeff, int accumulate, double2* Fout) {
+                                          double scale, double2* out, int stride) {
   using F = SpinFmt<(sizeof(R) == 8) ? DIRAC_F64 : DIRAC_F32>;
   const int j = nb_fwd<MU>(g, c, i);
   Cx<R> gf[12], pf[12];
@@ -312,7 +312,6 @@ __device__ __forceinline__ void force_dir(const Geom& g, const Rsrc& gr, const R
   project<MU, -1>(pf, b1);  // (1 - gamma) psi(n+mu)
   project<MU, 1>(pn, a2);   // (1 + gamma) psi(n)
   project<MU, 1>(gf, b2);   // (1 + gamma) g(n+mu)
-  double2* out = Fout + MU * 9;
 #pragma unroll
   for (int ra = 0; ra < 3; ++ra)
 #pragma unroll
@@ -326,34 +325,62 @@ __device__ __forceinline__ void force_dir(const Geom& g, const Rsrc& gr, const R
         re += (double)a2[s][ra].re * b2[s][cb].re + (double)a2[s][ra].im * b2[s][cb].im;
         im += (double)a2[s][ra].im * b2[s][cb].re - (double)a2[s][ra].re * b2[s][cb].im;
       }
-      re *= 0.5 * coeff;
-      im *= 0.5 * coeff;
-      double2 o = make_double2(re, im);
-      if (accumulate) {
-        double2 prev = out[ra * 3 + cb];
-        o.x += prev.x;
-        o.y += prev.y;
-      }
-      out[ra * 3 + cb] = o;
+      out[(MU * 9 + ra * 3 + cb) * stride] = make_double2(re * scale, im * scale);
     }
 }
 
+// One thread per site over 64 consecutive lexicographic sites (both
+// parities).  The output is the canonical [site][mu][3][3] complex128 array,
+// 576 contiguous bytes per site: each thread stages its 36 entries in LDS
+// (entry-major, so the writes are conflict-free) and the block then writes
+// its contiguous 64 x 576 bytes with fully coalesced stores (adding the
+// previous contents when accumulating).
+constexpr int kForceBlock = 64;
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_force(Geom g, int nb, const char* gin, const char* psi,
-                                                  uint32_t fbytes, double2* F, double coeff, int acc) {
-  SiteIdx s = site_idx(g, nb);
-  if (!s.valid) return;
-  using R = typename SpinFmt<P>::R;
-  const Rsrc gr = make_rsrc(gin, fbytes), pr = make_rsrc(psi, fbytes);
-  const Coord c = cb_coords(g, s.p, s.i);
-  Cx<R> gn[12], pn[12];
-  SpinFmt<P>::load(gr, g.Vh, s.p, s.i, gn);
-  SpinFmt<P>::load(pr, g.Vh, s.p, s.i, pn);
-  double2* out = F + (size_t)lex_site(g, s.p, s.i) * 36;
-  force_dir<0>(g, gr, pr, s.p, s.i, c, gn, pn, coeff, acc, out);
-  force_dir<1>(g, gr, pr, s.p, s.i, c, gn, pn, coeff, acc, out);
-  force_dir<2>(g, gr, pr, s.p, s.i, c, gn, pn, coeff, acc, out);
-  force_dir<3>(g, gr, pr, s.p, s.i, c, gn, pn, coeff, acc, out);
+__global__ void __launch_bounds__(kForceBlock) k_force(Geom g, int64_t V, const char* gin, const char* psi,
+                                                       uint32_t fbytes, double2* F, double coeff, int acc) {
+  __shared__ double2 stage[36 * kForceBlock];
+  const int tid = threadIdx.x;
+  const int64_t n0 = (int64_t)blockIdx.x * kForceBlock;
+  const int64_t n = n0 + tid;
+  if (n < V) {
+    using R = typename SpinFmt<P>::R;
+    Coord c;
+    int64_t r = n;
+    c.x = (int)(r % g.X);
+    r /= g.X;
+    c.y = (int)(r % g.Y);
+    r /= g.Y;
+    c.z = (int)(r % g.Z);
+    c.t = (int)(r / g.Z);
+    const int p = (c.x + c.y + c.z + c.t) & 1;
+    const int i = (int)(n >> 1);
+    const Rsrc gr = make_rsrc(gin, fbytes), pr = make_rsrc(psi, fbytes);
+    Cx<R> gn[12], pn[12];
+    SpinFmt<P>::load(gr, g.Vh, p, i, gn);
+    SpinFmt<P>::load(pr, g.Vh, p, i, pn);
+    const double scale = 0.5 * coeff;
+    force_dir<0>(g, gr, pr, p, i, c, gn, pn, scale, stage + tid, kForceBlock);
+    force_dir<1>(g, gr, pr, p, i, c, gn, pn, scale, stage + tid, kForceBlock);
+    force_dir<2>(g, gr, pr, p, i, c, gn, pn, scale, stage + tid, kForceBlock);
+    force_dir<3>(g, gr, pr, p, i, c, gn, pn, scale, stage + tid, kForceBlock);
+  }
+  __syncthreads();
+  const int nvals = (int)min((int64_t)kForceBlock, V - n0) * 36;
+  double2* out = F + n0 * 36;
+#pragma unroll 4
+  for (int k = 0; k < 36; ++k) {
+    const int s = k * kForceBlock + tid;  // position in the block's output
+    if (s < nvals) {
+      double2 v = stage[(s % 36) * kForceBlock + s / 36];
+      if (acc) {
+        const double2 prev = out[s];
+        v.x += prev.x;
+        v.y += prev.y;
+      }
+      out[s] = v;
+    }
+  }
 }
 
 }  // namespace
@@ -515,12 +542,13 @@ hipError_t zero(const Geom& g, int nrhs, FieldRef f, hipStream_t st) {
 
 hipError_t force(const Geom& g, int prec, const void* gin, const void* psi, uint32_t fbytes, void* F,
                  double coeff, int accumulate, hipStream_t st) {
-  SiteGrid sg = site_grid(g, 1);
+  const int64_t V = 2 * (int64_t)g.Vh;
+  const dim3 grid((unsigned)((V + kForceBlock - 1) / kForceBlock));
   if (prec == DIRAC_F64)
-    hipLaunchKernelGGL(k_force<DIRAC_F64>, sg.grid, dim3(kBlock), 0, st, g, sg.nb, (const char*)gin,
+    hipLaunchKernelGGL(k_force<DIRAC_F64>, grid, dim3(kForceBlock), 0, st, g, V, (const char*)gin,
                        (const char*)psi, fbytes, (double2*)F, coeff, accumulate);
   else if (prec == DIRAC_F32)
-    hipLaunchKernelGGL(k_force<DIRAC_F32>, sg.grid, dim3(kBlock), 0, st, g, sg.nb, (const char*)gin,
+    hipLaunchKernelGGL(k_force<DIRAC_F32>, grid, dim3(kForceBlock), 0, st, g, V, (const char*)gin,
                        (const char*)psi, fbytes, (double2*)F, coeff, accumulate);
   else
     return hipErrorInvalidValue;

@@ -139,9 +139,12 @@ int true_residual(Ctx& c, const void* eta, const void* x, int kind) {
   return dslash_sub(c, c.hi, c.Uhi, c.work + c.L.t, eta, c.work + c.L.r, DIRAC_F64, 0, kGateNone, kind);
 }
 
+// Iterations enqueued between host convergence checks: about 600 us of work,
+// at least 8 (an iteration past convergence is gated off inside its kernels
+// and costs only the launches, cheaper than a host round trip).
 int auto_check_every(const OpInfo& o) {
   const double iter_us = std::max(15.0, o.V * o.nrhs * 6e-4);
-  return (int)std::min(64.0, std::max(2.0, std::round(600.0 / iter_us)));
+  return (int)std::min(64.0, std::max(8.0, std::round(600.0 / iter_us)));
 }
 
 // Run CG iterations on (x, p, r) with the given operator until every

@@ -63,11 +63,23 @@ def test_sizes():
     (dict(link=10), abi.EINVAL),
     (dict(prec=abi.F16S, link=abi.LINK18), abi.EUNSUPPORTED),
     (dict(m_q=float("nan")), abi.EINVAL),
+    (dict(dims=(2048, 1024, 1024, 2)), abi.EINVAL),           # volume 2^32 >= 2^31
+    (dict(dims=(128, 128, 128, 4)), abi.EUNSUPPORTED),        # float64 18-real links 4.8 GB >= 4 GiB
+    (dict(dims=(256, 256, 256, 2), link=abi.LINK12), abi.EUNSUPPORTED),  # one spinor field 6.4 GB
 ])
 def test_invalid_op_rejected(kw, code):
     lib = abi.load()
     assert lib.dirac_spinor_bytes(C.byref(_op(**kw))) == code
     assert lib.dirac_last_error()
+
+
+def test_largest_accepted_sizes():
+    lib = abi.load()
+    # just under 4 GiB: 96^3 x 8 float64 18-real links, 4 076 863 488 bytes
+    op = _op(dims=(96, 96, 96, 8))
+    assert lib.dirac_gauge_bytes(C.byref(op)) == 96 ** 3 * 8 * 576 < 2 ** 32
+    assert lib.dirac_spinor_bytes(C.byref(op)) == 96 ** 3 * 8 * 192
+    assert lib.dirac_spinor_bytes(C.byref(_op(dims=(96, 96, 96, 8), nrhs=12))) == 12 * 96 ** 3 * 8 * 192
 
 
 def test_null_and_misaligned_pointers_rejected():

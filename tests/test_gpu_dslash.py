@@ -137,6 +137,31 @@ def test_stream_multi_rhs(prec, link, tol, remap):
         assert np.array_equal(got[k], single), k
 
 
+def test_largest_field_sampled():
+    # 96^3 x 8 in float64 with 18-real links: the links take 4 076 863 488
+    # bytes, just under the 4 GiB a buffer resource addresses.  The stencil
+    # does not need SU(3) links for 18-real storage, so complex Gaussian
+    # links (quick to draw) serve; 400 sampled sites against the oracle.
+    dims = (96, 96, 96, 8)
+    g = synth.rng(21)
+    shape_u = (dims[3], dims[2], dims[1], dims[0], 4, 3, 3)
+    U = g.standard_normal(shape_u) + 1j * g.standard_normal(shape_u)
+    psi = synth.spinor_gauss(dims, g)
+    m = 0.1
+    op = D.Operator(dims, m, "f64", 18)
+    assert op.gauge_bytes() < 2 ** 32 and op.gauge_bytes() > 0.94 * 2 ** 32
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    for dagger in (False, True):
+        got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
+        s = sample_sites(dims, 400, seed=5)
+        ref = wilson.dslash_at(U, psi, m, s, dagger=dagger)
+        assert rel_inf(got[s[:, 3], s[:, 2], s[:, 1], s[:, 0]], ref) <= 1e-13
+        del got
+    del Ui, pi
+    torch.cuda.empty_cache()
+
+
 def test_pack_roundtrips():
     dims = (4, 2, 6, 2)
     U, psi = inputs(dims, "haar", seed=6)
