@@ -422,6 +422,9 @@ def main(argv=None):
                     help="size of the plain copy measured as the bandwidth ceiling (0: skip)")
     ap.add_argument("--headline-launch", default=None,
                     help="JSON launch configuration of the headline Dslash (no tuning); for profiling runs")
+    ap.add_argument("--profile-cg", action="store_true",
+                    help="only the 32^3x64 CG solves (float64, F32 and F16S inner), one JSON line; "
+                         "for kernel traces of the solver (run after a full bench with DIRAC_TUNE_CACHE set)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); "
@@ -432,6 +435,13 @@ def main(argv=None):
     from paper_1904_08616_amd import dirac as D
 
     torch.cuda.set_device(0)
+    if a.profile_cg:
+        big = (32, 32, 32, 64)
+        log("generating 32^3x64 inputs")
+        Ub, pb = gen_inputs(big, seed=0)
+        res = {inner: cg_time(torch, D, big, Ub, pb, 0.02, inner, link=12) for inner in ("f64", "f32", "f16s")}
+        print(json.dumps({"cg_32x32x32x64_m0.02_link12": res}), flush=True)
+        return 0
     dims = (16, 16, 16, 32)
     V = int(np.prod(dims))
     m_q = 0.05
