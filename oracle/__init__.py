@@ -18,7 +18,10 @@ against the paper rather than to be fast:
 * ``solvers``   -- textbook CG on D^dagger D and an emulation of the mixed
                    precision "Residual Guided CG" of Algorithm 1;
 * ``force``     -- the gradient of a real loss with respect to the links
-                   (projected spinor outer products).
+                   (projected spinor outer products);
+* ``evenodd``   -- the even-odd (Schur complement) form of D x = b: the
+                   even-site operator D_hat = A - K_eo K_oe / A, the reduced
+                   source, the odd-site reconstruction and the solve.
 
 Conventions: canonical arrays as in ``synth`` (links ``[T,Z,Y,X,4,3,3]``,
 spinors ``[T,Z,Y,X,4,3]``, direction mu = 0..3 <-> x,y,z,t), periodic
@@ -31,4 +34,4 @@ gauge and translation covariance, dense linear solves, and finite
 differences of the operator.  None is "parity unpinned".
 """
 
-from . import gamma, wilson, freefield, solvers, force, lowprec  # noqa: F401
+from . import gamma, wilson, freefield, solvers, force, lowprec, evenodd  # noqa: F401
