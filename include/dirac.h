@@ -187,6 +187,54 @@ int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const vo
              void* work, int64_t work_bytes, const cg_params* params, cg_stats* stats,
              void* stream);
 
+/* ----------------------------------------------------- even-odd form ---- */
+
+/* Not a method of the paper: the even-odd (Schur complement) form of D.
+ * Every hop of eq. (1) joins sites of opposite parity ((x+y+z+t) mod 2) and
+ * the mass term stays on its site, so in (even, odd) blocks
+ *   D = [[A, K_eo], [K_oe, A]],   A = m_q + 4,
+ * with K the hopping sum of eq. (1) (its factor 1/2 included), and the
+ * even-site Schur complement is
+ *   D_hat = A - K_eo K_oe / A.
+ * D^dagger has the same form with the adjoint hop (the projector swap of
+ * dirac_dagger_apply), and its Schur complement is D_hat^dagger.
+ *
+ * Even vectors live in the even-parity plane of an ordinary internal field of
+ * op (the layout of dirac_pack_spinor); the odd plane is ignored or used as
+ * scratch as stated. */
+
+/* out_e = D_hat in_e (dagger = 0) or D_hat^dagger in_e (dagger = 1), for
+ * each of op->nrhs fields.  op: DIRAC_F64 or DIRAC_F32 (either link
+ * storage).  Only the even plane of `in` is read.  The even plane of `out`
+ * receives the result; its odd plane is overwritten with the intermediate
+ * K_oe in_e.  in and out must not overlap (DIRAC_EINVAL).  Asynchronous. */
+int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int, void* out_int, int32_t dagger,
+                      void* stream);
+
+/* Bytes of scratch cg_solve_eo needs (params->inner_prec DIRAC_F64 or
+ * DIRAC_F32; DIRAC_EUNSUPPORTED otherwise). */
+int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params);
+
+/* Solve D x = b (eq. (1)) for each of op_hi->nrhs sources through the
+ * Schur complement:
+ *   b_hat = b_e - K_eo b_o / A,
+ *   D_hat^dagger D_hat x_e = D_hat^dagger b_hat   (cg_solve's CG: plain
+ *       float64 for inner_prec = DIRAC_F64, Algorithm 1 with a float32 inner
+ *       solve for DIRAC_F32; the 16-bit formats are not supported here),
+ *   x_o = (b_o - K_oe x_e) / A.
+ * A source has converged when ||b - D x|| / ||b|| < params->tol, recomputed
+ * in float64 on the full lattice after the reconstruction; until then the
+ * CG tolerance on the normal equations (first 0.25 tol) is tightened and the
+ * solve resumed from the current x (at most 6 passes, max_iter CG
+ * iterations in all).
+ * Arguments as for cg_solve, with b in place of eta; x: the even plane holds
+ * the initial guess on entry, x the full solution on exit.  stats: iters
+ * and outer summed over the passes, dslash_hi / dslash_lo count applications
+ * of D_hat or D_hat^dagger, true_rel_res = ||b - D x|| / ||b||.
+ * Synchronises the stream.  (D^dagger D x = eta itself is cg_solve's.) */
+int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* b, void* x, void* work,
+                int64_t work_bytes, const cg_params* params, cg_stats* stats, void* stream);
+
 /* ------------------------------------------------------------ gradient ---- */
 
 /* Link gradient of a real loss L through chi = D(U) psi (the backward of

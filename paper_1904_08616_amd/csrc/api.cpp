@@ -145,6 +145,10 @@ DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out
   a.remap = 1;
   a.sub_alpha = 0;
   a.gate = kGateNone;
+  a.par = -1;
+  a.ctr = nullptr;
+  a.ctr_stride = 0;
+  a.hop_c = 1.0;
   return a;
 }
 
@@ -423,6 +427,37 @@ int dirac_mdagm_apply(const dirac_op* op, const void* U_int, const void* psi_int
     return set_error(DIRAC_EINVAL, "dirac_mdagm_apply: tmp overlaps another buffer");
   CHECK(apply_common(op, U_int, psi_int, tmp_int, stream, 0, "dirac_mdagm_apply"));
   return apply_common(op, U_int, tmp_int, chi_int, stream, 1, "dirac_mdagm_apply");
+}
+
+int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int, void* out_int, int32_t dagger,
+                      void* stream) {
+  clear_error();
+  const char* what = "dirac_schur_apply";
+  OpInfo o;
+  CHECK(check_op(op, &o, what));
+  if (o.prec != DIRAC_F64 && o.prec != DIRAC_F32) return set_error(DIRAC_EUNSUPPORTED, "%s: F64 or F32 only", what);
+  CHECK(check_ptr(U_int, "U_int", what));
+  CHECK(check_ptr(in_int, "in_int", what));
+  CHECK(check_ptr(out_int, "out_int", what));
+  const int64_t sb = spinor_buffer_bytes(o);
+  if (overlap(in_int, sb, out_int, sb) || overlap(U_int, o.gauge_bytes, out_int, sb))
+    return set_error(DIRAC_EINVAL, "%s: output overlaps an input", what);
+  const int dag = dagger ? 1 : 0;
+  const double A = o.m_q + 4.0;
+  hipStream_t st = (hipStream_t)stream;
+  // out_o = K_oe in_e, then out_e = A in_e - K_eo out_o / A
+  DslashArgs a = dslash_args(o, U_int, in_int, out_int);
+  a.par = 1;
+  a.hop_c = 1.0;
+  a.mass4 = 0.0;
+  CHECK(run_hop(o.prec, o.link, dag, kEpiStore, a, st));
+  a = dslash_args(o, U_int, out_int, out_int);
+  a.par = 0;
+  a.ctr = (const char*)in_int;
+  a.ctr_stride = o.field_stride;
+  a.mass4 = A;
+  a.hop_c = -1.0 / A;
+  return run_hop(o.prec, o.link, dag, kEpiStore, a, st);
 }
 
 int dirac_field_dot(const dirac_op* op, const void* a, const void* b, double* out_host, void* stream) {

@@ -52,6 +52,12 @@ struct DslashArgs {
   int nt_store;      // non-temporal output stores (kEpiStore / kEpiStoreNorm)
   int sy, sz, tc;    // streaming kernel: tile rows in y, planes in z, t slices per block
   RedArgs red;
+  // half-lattice hop (even-odd form): output parity, centre field and the
+  // hop coefficient of out = mass4 * ctr + hop_c * (1/2) sum of hops
+  int par;
+  const char* ctr;   // null: no centre term
+  int64_t ctr_stride;
+  double hop_c;
 };
 
 template <class To, class From>

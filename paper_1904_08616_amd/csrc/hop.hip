@@ -1,0 +1,137 @@
+// Half-lattice hops: the even-odd (Schur complement) form of D.
+//
+// Every hop of eq. (1) joins sites of opposite parity and the mass term stays
+// on its site, so in (even, odd) blocks D = [[A, K_eo], [K_oe, A]] with
+// A = m_q + 4 and K the hopping sum (its factor 1/2 included).  One launch
+// here computes, on the sites of one parity p only,
+//     out(n) = mass4 * ctr(n) + hop_c * (K in)(n),
+// reading `in` on the other parity (the hops of eq. (1), projectors swapped
+// for the adjoint) and the centre field `ctr` on p; with ctr null there is no
+// centre term.  Two launches make the Schur complement
+//     D_hat = A - K_eo K_oe / A
+// (bare hop into the odd sites, then centre A and hop coefficient -1/A on the
+// even sites), and with the adjoint hop D_hat^dagger.  Fields keep the full
+// layout; a launch touches only the plane of its output parity, so one
+// buffer can hold an even vector and the odd intermediate of the same
+// operator.  Epilogues as in the full stencil: store, store plus |out|^2, or
+// dst = src - alpha out plus |dst|^2.
+//
+// One thread per output site and right-hand side (the per-site stencil's
+// hop code); the grid covers one parity only.
+#include "lib.h"
+
+namespace dirac {
+
+namespace {
+
+constexpr int kHopBlock = 128;
+
+template <int P, int LK, bool DAG, int EPI>
+__global__ void __launch_bounds__(kHopBlock) __attribute__((amdgpu_waves_per_eu(dslash_waves<P, 1>())))
+k_hop(DslashArgs a) {
+  using SF = SpinFmt<P>;
+  using Rl = typename SF::R;
+  const int Vh = a.g.Vh;
+  const int l = xcd_tile(blockIdx.x, a.ntiles * a.ngroups, a.remap);
+  const int rhs = l % a.ngroups;  // right-hand sides of one tile side by side
+  const int tile = l / a.ngroups;
+  const int p = a.par;
+  const int i = tile * kHopBlock + threadIdx.x;
+  bool on = i < Vh;
+  if (on && a.gate == kGateNotDone) on = !a.red.state[rhs].done;
+  if (on && a.gate == kGateActive) on = a.red.state[rhs].active != 0;
+  double vals[1][1] = {{0.0}};
+  if (on) {
+    const Coord c = cb_coords(a.g, p, i);
+    const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
+    const Rsrc in[1] = {make_rsrc(a.in + (size_t)rhs * a.in_stride, a.field_bytes)};
+    const bool onr[1] = {true};
+    Cx<Rl> acc[1][12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[0][k] = {Rl(0), Rl(0)};
+    hop_dir<P, LK, DAG, 1, 0>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<P, LK, DAG, 1, 1>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<P, LK, DAG, 1, 2>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<P, LK, DAG, 1, 3>(a, Ur, in, c, p, i, onr, acc);
+
+    const Rl ch = (Rl)(0.5 * a.hop_c);
+    Cx<Rl> o[12];
+    if (a.ctr != nullptr) {
+      Cx<Rl> v[12];
+      SF::load(make_rsrc(a.ctr + (size_t)rhs * a.ctr_stride, a.field_bytes), Vh, p, i, v);
+      const Rl cm = (Rl)a.mass4;
+#pragma unroll
+      for (int k = 0; k < 12; ++k)
+        o[k] = {fma(cm, v[k].re, ch * acc[0][k].re), fma(cm, v[k].im, ch * acc[0][k].im)};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) o[k] = {ch * acc[0][k].re, ch * acc[0][k].im};
+    }
+    if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+      const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
+      SF::store(orsrc, Vh, p, i, o);
+      if constexpr (EPI == kEpiStoreNorm) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        vals[0][0] = s;
+      }
+    } else {
+      const Rl cf = a.sub_alpha ? (Rl)a.red.state[rhs].alpha : Rl(1);
+      Cx<Rl> d[12];
+      SF::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        d[k].re = fma(-cf, o[k].re, d[k].re);
+        d[k].im = fma(-cf, o[k].im, d[k].im);
+        s += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+      }
+      SF::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, d);
+      vals[0][0] = s;
+    }
+  }
+  if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, tile, a.ntiles);
+}
+
+template <int P, int LK, bool DAG, int EPI>
+hipError_t launch_hop(DslashArgs a, hipStream_t st) {
+  a.ngroups = a.nrhs;
+  a.ntiles = (a.g.Vh + kHopBlock - 1) / kHopBlock;
+  hipLaunchKernelGGL((k_hop<P, LK, DAG, EPI>), dim3(a.ntiles * a.ngroups), dim3(kHopBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || EPI == kEpiStore) return e;
+  return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);
+}
+
+template <int P, int LK>
+hipError_t hop_dispatch(int dag, int epi, const DslashArgs& a, hipStream_t st) {
+  if (dag) {
+    if (epi == kEpiStore) return launch_hop<P, LK, true, kEpiStore>(a, st);
+    if (epi == kEpiStoreNorm) return launch_hop<P, LK, true, kEpiStoreNorm>(a, st);
+    return launch_hop<P, LK, true, kEpiSubNorm>(a, st);
+  }
+  if (epi == kEpiStore) return launch_hop<P, LK, false, kEpiStore>(a, st);
+  if (epi == kEpiStoreNorm) return launch_hop<P, LK, false, kEpiStoreNorm>(a, st);
+  return launch_hop<P, LK, false, kEpiSubNorm>(a, st);
+}
+
+}  // namespace
+
+int hop_partials(const Geom& g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
+
+int run_hop(int prec, int link, int dag, int epi, DslashArgs a, hipStream_t st) {
+  if (a.par != 0 && a.par != 1) return set_error(DIRAC_EINVAL, "half-lattice hop: parity must be 0 or 1");
+  if (epi != kEpiStore && epi != kEpiStoreNorm && epi != kEpiSubNorm)
+    return set_error(DIRAC_EINVAL, "half-lattice hop: unknown epilogue %d", epi);
+  a.remap = 1;
+  hipError_t e;
+  if (prec == DIRAC_F64 && link == 18) e = hop_dispatch<DIRAC_F64, 18>(dag, epi, a, st);
+  else if (prec == DIRAC_F64 && link == 12) e = hop_dispatch<DIRAC_F64, 12>(dag, epi, a, st);
+  else if (prec == DIRAC_F32 && link == 18) e = hop_dispatch<DIRAC_F32, 18>(dag, epi, a, st);
+  else if (prec == DIRAC_F32 && link == 12) e = hop_dispatch<DIRAC_F32, 12>(dag, epi, a, st);
+  else return set_error(DIRAC_EUNSUPPORTED, "half-lattice hop: F64 or F32 only (prec %d link %d)", prec, link);
+  return hip_status(e, "half-lattice hop launch");
+}
+
+}  // namespace dirac

@@ -54,6 +54,13 @@ int run_dslash(int pin, int pout, int link, int dag, int epi, const LaunchCfg& c
 
 DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out);
 
+// Half-lattice hop of the even-odd form (hop.hip): on the sites of parity
+// a.par, out = a.mass4 * ctr + a.hop_c * (K in) with the epilogue `epi`;
+// F64 and F32 with either link storage.  hop_partials: reduction partials
+// per right-hand side of one launch.
+int run_hop(int prec, int link, int dag, int epi, DslashArgs a, hipStream_t st);
+int hop_partials(const Geom& g);
+
 // Library-owned device scratch for reductions of API calls (grown on
 // demand, one per device).
 struct Scratch {

@@ -28,6 +28,16 @@
 // at most twice the first cycle's count.  Two capped cycles in a row, or six
 // cycles without progress, mean the low-precision operator cannot reach the
 // target and the solve finishes in float64.
+//
+// The even-odd form (cg_solve_eo) runs the same machinery on the normal
+// equations of the even-site Schur complement, D_hat^dagger D_hat x_e =
+// D_hat^dagger b_hat, for the system D x = b: the two operator applications
+// of an iteration become two half-lattice hops each, and the vector
+// operations act on the even planes of the fields only (the even plane of a
+// field, read as a field of half as many sites, has the same elementwise
+// structure).  The odd sites are reconstructed afterwards and the residual
+// ||b - D x|| checked on the full lattice; if it is still above the target,
+// the CG tolerance is tightened and the solve resumed from the current x.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,11 +53,11 @@ namespace dirac {
 namespace {
 
 struct Layout {
-  int64_t state, partials, r, p, t, r0, psi, plo, tlo, total;
+  int64_t state, partials, r, p, t, r0, psi, plo, tlo, eh, total;
   int64_t nparts;  // partial slots per right-hand side
 };
 
-Layout layout(const OpInfo& hi, int inner_prec) {
+Layout layout(const OpInfo& hi, int inner_prec, bool eo = false) {
   Layout L;
   int64_t off = 0;
   auto take = [&](int64_t bytes) {
@@ -73,12 +83,15 @@ Layout layout(const OpInfo& hi, int inner_prec) {
   } else {
     L.r0 = L.psi = L.plo = L.tlo = -1;
   }
+  L.eh = eo ? take(f64) : -1;  // even-odd form: the source of the normal equations
   L.total = off;
   return L;
 }
 
 struct Ctx {
   OpInfo hi, lo;
+  bool eo = false;  // operator: D_hat of the even-odd form instead of D
+  Geom vg;          // geometry of the vector operations (even planes only when eo)
   const void* Uhi;
   const void* Ulo;
   char* work;
@@ -109,8 +122,34 @@ RedArgs to_args(const RedTarget& t) { return RedArgs{t.partials, t.state, t.kind
 // sqrt of a reduced norm^2; NaN stays NaN (std::max would turn it into 0).
 double norm_of(double v) { return std::isnan(v) ? v : std::sqrt(v > 0.0 ? v : 0.0); }
 
-// t = D in (store + |t|^2 into `kind`), for precision op o.
+// Half-lattice hop: on the sites of parity par, out = cm * ctr + ch * K in
+// (K of D^dagger when dag), with epilogue epi; src and use_alpha for the
+// subtraction epilogue.
+int hop(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void* ctr, void* out, int par,
+        int dag, double cm, double ch, int epi, int gate, int kind, const void* src = nullptr, int use_alpha = 0) {
+  DslashArgs a = dslash_args(o, U, in, out);
+  a.par = par;
+  a.ctr = (const char*)ctr;
+  a.ctr_stride = o.field_stride;
+  a.mass4 = cm;
+  a.hop_c = ch;
+  a.gate = gate;
+  a.red = to_args(c.red(kind));
+  a.src = (const char*)src;
+  a.src_stride = o.field_stride;
+  a.sub_alpha = use_alpha;
+  return run_hop(o.prec, o.link, dag, epi, a, c.st);
+}
+
+// t = D in (store + |t|^2 into `kind`), for precision op o.  Even-odd form:
+// t_e = D_hat in_e, with the odd plane of t holding the intermediate K_oe in_e.
 int dslash_norm(const Ctx& c, const OpInfo& o, const void* U, const void* in, void* t, int gate, int kind) {
+  if (c.eo) {
+    const double A = o.m_q + 4.0;
+    int rc = hop(c, o, U, in, nullptr, t, 1, 0, 0.0, 1.0, kEpiStore, gate, kFinPlain);
+    if (rc != DIRAC_OK) return rc;
+    return hop(c, o, U, t, in, t, 0, 0, A, -1.0 / A, kEpiStoreNorm, gate, kind);
+  }
   DslashArgs a = dslash_args(o, U, in, t);
   a.gate = gate;
   a.red = to_args(c.red(kind));
@@ -118,8 +157,17 @@ int dslash_norm(const Ctx& c, const OpInfo& o, const void* U, const void* in, vo
 }
 
 // dst = src - coef * D^dag in, |dst|^2 into `kind`; dst has precision dprec.
+// Even-odd form: dst_e = src_e - coef * D_hat^dagger in_e, and the odd plane
+// of `in` (a workspace field) receives the intermediate.
 int dslash_sub(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void* src, void* dst, int dprec,
                int use_alpha, int gate, int kind) {
+  if (c.eo) {
+    if (dprec != o.prec) return set_error(DIRAC_EUNSUPPORTED, "even-odd residual update: mixed formats");
+    const double A = o.m_q + 4.0;
+    int rc = hop(c, o, U, in, nullptr, (void*)in, 1, 1, 0.0, 1.0, kEpiStore, gate, kFinPlain);
+    if (rc != DIRAC_OK) return rc;
+    return hop(c, o, U, in, in, dst, 0, 1, A, -1.0 / A, kEpiSubNorm, gate, kind, src, use_alpha);
+  }
   DslashArgs a = dslash_args(o, U, in, dst);
   const FieldRef d = field_as(c.hi, dprec, dst);
   a.out_bytes = d.bytes;
@@ -157,7 +205,7 @@ int run_iterations(Ctx& c, const OpInfo& o, const void* U, FieldRef x, FieldRef 
       if (rc != DIRAC_OK) return rc;
       rc = dslash_sub(c, o, U, t.ptr, r.ptr, r.ptr, r.prec, 1, kGateActive, kFinRho);
       if (rc != DIRAC_OK) return rc;
-      rc = hip_status(cg_xp_update(c.hi.g, c.hi.nrhs, x, p, r, c.dstate, c.st), "cg update");
+      rc = hip_status(cg_xp_update(c.vg, c.hi.nrhs, x, p, r, c.dstate, c.st), "cg update");
       if (rc != DIRAC_OK) return rc;
     }
     int rc = c.pull();
@@ -169,7 +217,7 @@ int run_iterations(Ctx& c, const OpInfo& o, const void* U, FieldRef x, FieldRef 
 }
 
 int eta_norms(Ctx& c, const void* eta, std::vector<double>& en) {
-  int rc = hip_status(norm2(c.hi.g, c.hi.nrhs, field_of(c.hi, eta), c.red(kFinPlain), c.st), "norm");
+  int rc = hip_status(norm2(c.vg, c.hi.nrhs, field_of(c.hi, eta), c.red(kFinPlain), c.st), "norm");
   if (rc != DIRAC_OK) return rc;
   rc = c.pull();
   if (rc != DIRAC_OK) return rc;
@@ -230,7 +278,7 @@ int cg_f64(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::ve
     if (!any) return DIRAC_OK;
     rc = c.push();
     if (rc != DIRAC_OK) return rc;
-    rc = hip_status(convert_scale(c.hi.g, n, R, P, nullptr, -1, nullptr, c.st), "copy");  // p = r
+    rc = hip_status(convert_scale(c.vg, n, R, P, nullptr, -1, nullptr, c.st), "copy");  // p = r
     if (rc != DIRAC_OK) return rc;
     rc = run_iterations(c, c.hi, c.Uhi, X, P, R, T, check_every);
     if (rc != DIRAC_OK) return rc;
@@ -260,7 +308,7 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
   std::vector<int> stall(n, 0), used(n, 0), capped(n, 0), n_first(n, -1), n_cap(n, kmax);
   *fallback = false;
 
-  int rc = hip_status(zero(c.hi.g, n, PLO, c.st), "zero");
+  int rc = hip_status(zero(c.vg, n, PLO, c.st), "zero");
   if (rc != DIRAC_OK) return rc;
   rc = true_residual(c, eta, x, kFinPlain);
   if (rc != DIRAC_OK) return rc;
@@ -298,10 +346,10 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
     rc = c.push();
     if (rc != DIRAC_OK) return rc;
     RedTarget rt = c.red(kFinRhoSet);
-    rc = hip_status(convert_scale(c.hi.g, n, R, R0, c.dstate, 0, &rt, c.st), "cast");
+    rc = hip_status(convert_scale(c.vg, n, R, R0, c.dstate, 0, &rt, c.st), "cast");
     if (rc != DIRAC_OK) return rc;
     // carried direction: <r0, p_k>
-    rc = hip_status(dot(c.hi.g, n, R0, PLO, c.red(kFinPlain), c.st), "dot");
+    rc = hip_status(dot(c.vg, n, R0, PLO, c.red(kFinPlain), c.st), "dot");
     if (rc != DIRAC_OK) return rc;
     rc = c.pull();
     if (rc != DIRAC_OK) return rc;
@@ -334,9 +382,9 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
     }
     rc = c.push();
     if (rc != DIRAC_OK) return rc;
-    rc = hip_status(axpby(c.hi.g, n, R0, PLO, c.dstate, 0, 0, 0, 0, c.st), "restart direction");
+    rc = hip_status(axpby(c.vg, n, R0, PLO, c.dstate, 0, 0, 0, 0, c.st), "restart direction");
     if (rc != DIRAC_OK) return rc;
-    rc = hip_status(zero(c.hi.g, n, PSI, c.st), "zero");
+    rc = hip_status(zero(c.vg, n, PSI, c.st), "zero");
     if (rc != DIRAC_OK) return rc;
 
     rc = run_iterations(c, c.lo, c.Ulo, PSI, PLO, R0, TLO, check_every);
@@ -366,7 +414,7 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
       }
     rc = c.push();
     if (rc != DIRAC_OK) return rc;
-    rc = hip_status(axpby(c.hi.g, n, PSI, X, c.dstate, 0, 0, 0, 0, c.st), "accumulate");
+    rc = hip_status(axpby(c.vg, n, PSI, X, c.dstate, 0, 0, 0, 0, c.st), "accumulate");
     if (rc != DIRAC_OK) return rc;
     rc = true_residual(c, eta, x, kFinPlain);
     if (rc != DIRAC_OK) return rc;
@@ -404,6 +452,83 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
   }
 }
 
+// Validation and context of a solve (cg_solve and cg_solve_eo).
+int prepare(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* eta, void* x, void* work,
+            int64_t work_bytes, const cg_params* params, cg_stats* stats_out, bool eo, const char* what, Ctx& c,
+            cg_params& prm, void* stream) {
+  OpInfo hi;
+  int rc = check_op(op_hi, &hi, what);
+  if (rc != DIRAC_OK) return rc;
+  if (hi.prec != DIRAC_F64) return set_error(DIRAC_EINVAL, "%s: op_hi must be DIRAC_F64", what);
+  if (params == nullptr || stats_out == nullptr) return set_error(DIRAC_EINVAL, "%s: NULL params/stats", what);
+  prm = *params;
+  if (!(prm.tol > 0) || !std::isfinite(prm.tol)) return set_error(DIRAC_EINVAL, "%s: tol must be > 0", what);
+  if (prm.max_iter < 1) return set_error(DIRAC_EINVAL, "%s: max_iter must be >= 1", what);
+  if (!std::isfinite(prm.inner_delta)) return set_error(DIRAC_EINVAL, "%s: inner_delta must be finite", what);
+  const int ip = prm.inner_prec;
+  if (ip != DIRAC_F64 && ip != DIRAC_F32 && ip != DIRAC_F16S && ip != DIRAC_BF16S)
+    return set_error(DIRAC_EINVAL, "%s: unknown inner_prec %d", what, ip);
+  if (eo && ip != DIRAC_F64 && ip != DIRAC_F32)
+    return set_error(DIRAC_EUNSUPPORTED, "%s: inner_prec must be DIRAC_F64 or DIRAC_F32", what);
+  if (!U_hi || !eta || !x || !work) return set_error(DIRAC_EINVAL, "%s: NULL buffer", what);
+  if (ip != DIRAC_F64 && !U_lo) return set_error(DIRAC_EINVAL, "%s: U_lo is NULL for a mixed solve", what);
+  if ((((uintptr_t)U_hi | (uintptr_t)eta | (uintptr_t)x | (uintptr_t)work | (uintptr_t)U_lo) & 255u) != 0)
+    return set_error(DIRAC_EINVAL, "%s: buffers must be 256-byte aligned", what);
+  Layout L = layout(hi, ip, eo);
+  if (work_bytes < L.total)
+    return set_error(DIRAC_EWORKSPACE, "%s: workspace needs %lld bytes, got %lld", what, (long long)L.total,
+                     (long long)work_bytes);
+  const int64_t sb = hi.nrhs * hi.field_stride;
+  auto ov = [](const void* a, int64_t na, const void* b, int64_t nb) {
+    const char* p = (const char*)a;
+    const char* q = (const char*)b;
+    return p < q + nb && q < p + na;
+  };
+  if (ov(eta, sb, x, sb) || ov(work, L.total, x, sb) || ov(work, L.total, eta, sb) ||
+      ov(work, L.total, U_hi, hi.gauge_bytes))
+    return set_error(DIRAC_EINVAL, "%s: buffers overlap", what);
+
+  c.hi = hi;
+  c.lo = hi;
+  c.eo = eo;
+  c.vg = hi.g;
+  if (eo) c.vg.Vh = hi.g.Vh / 2;  // the even plane as a field of V/2 sites (V is a multiple of 16)
+  if (ip != DIRAC_F64) {
+    dirac_op lo = *op_hi;
+    lo.prec = ip;
+    lo.link = (ip == DIRAC_F32) ? op_hi->link : DIRAC_LINK12;
+    rc = check_op(&lo, &c.lo, what);
+    if (rc != DIRAC_OK) return rc;
+  }
+  c.Uhi = U_hi;
+  c.Ulo = U_lo;
+  c.work = (char*)work;
+  c.L = L;
+  c.st = (hipStream_t)stream;
+  c.dstate = (CgState*)(c.work + L.state);
+  c.hstate.assign(kMaxRhs, CgState{});
+  std::memset(c.hstate.data(), 0, sizeof(CgState) * kMaxRhs);
+  return c.push();
+}
+
+// The solve proper on A x = eta (A = D^dag D, or D_hat^dag D_hat in the
+// even-odd form): Algorithm 1 with a low-precision inner solve, finishing in
+// float64 if that falls back, or plain float64 CG.
+int solve_with(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::vector<double>& en,
+               std::vector<cg_stats>& stats) {
+  const int ip = prm.inner_prec;
+  const int check_every = prm.check_every > 0 ? prm.check_every : auto_check_every(ip == DIRAC_F64 ? c.hi : c.lo);
+  bool fallback = false;
+  int rc = DIRAC_OK;
+  if (ip != DIRAC_F64) rc = cg_mixed(c, eta, x, prm, en, stats, check_every, &fallback);
+  if (rc == DIRAC_OK && (ip == DIRAC_F64 || fallback)) {
+    for (size_t k = 0; k < stats.size(); ++k)
+      if (stats[k].status != DIRAC_EBREAKDOWN && en[k] != 0.0) stats[k].status = DIRAC_ENOCONV;
+    rc = cg_f64(c, eta, x, prm, en, stats, check_every);
+  }
+  return rc;
+}
+
 }  // namespace
 
 }  // namespace dirac
@@ -428,76 +553,22 @@ int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const vo
              int64_t work_bytes, const cg_params* params, cg_stats* stats_out, void* stream) {
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
-  OpInfo hi;
-  int rc = check_op(op_hi, &hi, "cg_solve");
-  if (rc != DIRAC_OK) return rc;
-  if (hi.prec != DIRAC_F64) return set_error(DIRAC_EINVAL, "cg_solve: op_hi must be DIRAC_F64");
-  if (params == nullptr || stats_out == nullptr) return set_error(DIRAC_EINVAL, "cg_solve: NULL params/stats");
-  cg_params prm = *params;
-  if (!(prm.tol > 0) || !std::isfinite(prm.tol)) return set_error(DIRAC_EINVAL, "cg_solve: tol must be > 0");
-  if (prm.max_iter < 1) return set_error(DIRAC_EINVAL, "cg_solve: max_iter must be >= 1");
-  if (!std::isfinite(prm.inner_delta)) return set_error(DIRAC_EINVAL, "cg_solve: inner_delta must be finite");
-  const int ip = prm.inner_prec;
-  if (ip != DIRAC_F64 && ip != DIRAC_F32 && ip != DIRAC_F16S && ip != DIRAC_BF16S)
-    return set_error(DIRAC_EINVAL, "cg_solve: unknown inner_prec %d", ip);
-  if (!U_hi || !eta || !x || !work) return set_error(DIRAC_EINVAL, "cg_solve: NULL buffer");
-  if (ip != DIRAC_F64 && !U_lo) return set_error(DIRAC_EINVAL, "cg_solve: U_lo is NULL for a mixed solve");
-  if ((((uintptr_t)U_hi | (uintptr_t)eta | (uintptr_t)x | (uintptr_t)work | (uintptr_t)U_lo) & 255u) != 0)
-    return set_error(DIRAC_EINVAL, "cg_solve: buffers must be 256-byte aligned");
-  Layout L = layout(hi, ip);
-  if (work_bytes < L.total)
-    return set_error(DIRAC_EWORKSPACE, "cg_solve: workspace needs %lld bytes, got %lld", (long long)L.total,
-                     (long long)work_bytes);
-  const int64_t sb = hi.nrhs * hi.field_stride;
-  auto ov = [](const void* a, int64_t na, const void* b, int64_t nb) {
-    const char* p = (const char*)a;
-    const char* q = (const char*)b;
-    return p < q + nb && q < p + na;
-  };
-  if (ov(eta, sb, x, sb) || ov(work, L.total, x, sb) || ov(work, L.total, eta, sb) ||
-      ov(work, L.total, U_hi, hi.gauge_bytes))
-    return set_error(DIRAC_EINVAL, "cg_solve: buffers overlap");
-
   Ctx c;
-  c.hi = hi;
-  c.lo = hi;
-  if (ip != DIRAC_F64) {
-    dirac_op lo = *op_hi;
-    lo.prec = ip;
-    lo.link = (ip == DIRAC_F32) ? op_hi->link : DIRAC_LINK12;
-    rc = check_op(&lo, &c.lo, "cg_solve (inner)");
-    if (rc != DIRAC_OK) return rc;
-  }
-  c.Uhi = U_hi;
-  c.Ulo = U_lo;
-  c.work = (char*)work;
-  c.L = L;
-  c.st = (hipStream_t)stream;
-  c.dstate = (CgState*)(c.work + L.state);
-  c.hstate.assign(kMaxRhs, CgState{});
-  std::memset(c.hstate.data(), 0, sizeof(CgState) * kMaxRhs);
-  rc = c.push();
+  cg_params prm;
+  int rc = prepare(op_hi, U_hi, U_lo, eta, x, work, work_bytes, params, stats_out, false, "cg_solve", c, prm, stream);
   if (rc != DIRAC_OK) return rc;
-
-  const int n = hi.nrhs;
+  const int n = c.hi.nrhs;
   std::vector<cg_stats> stats(n);
   for (auto& s : stats) {
     std::memset(&s, 0, sizeof(s));
     s.status = DIRAC_ENOCONV;
   }
-  const int check_every = prm.check_every > 0 ? prm.check_every : auto_check_every(ip == DIRAC_F64 ? hi : c.lo);
   std::vector<double> en(n, 0.0);
   rc = eta_norms(c, eta, en);
   if (rc == DIRAC_OK) {
     for (int k = 0; k < n; ++k)
       if (!std::isfinite(en[k])) stats[k].status = DIRAC_EBREAKDOWN;
-  }
-  bool fallback = false;
-  if (rc == DIRAC_OK && ip != DIRAC_F64) rc = cg_mixed(c, eta, x, prm, en, stats, check_every, &fallback);
-  if (rc == DIRAC_OK && (ip == DIRAC_F64 || fallback)) {
-    for (auto& s : stats)
-      if (s.status != DIRAC_EBREAKDOWN) s.status = DIRAC_ENOCONV;
-    rc = cg_f64(c, eta, x, prm, en, stats, check_every);
+    rc = solve_with(c, eta, x, prm, en, stats);
   }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int overall = DIRAC_OK;
@@ -513,6 +584,121 @@ int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const vo
   if (rc != DIRAC_OK) return rc;
   if (overall != DIRAC_OK)
     set_error(overall, "cg_solve: not every right-hand side converged (first status %d)", overall);
+  return overall;
+}
+
+int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params) {
+  clear_error();
+  OpInfo hi;
+  int rc = check_op(op_hi, &hi, "cg_workspace_bytes_eo");
+  if (rc != DIRAC_OK) return rc;
+  if (params == nullptr) return set_error(DIRAC_EINVAL, "cg_workspace_bytes_eo: params is NULL");
+  const int ip = params->inner_prec;
+  if (ip != DIRAC_F64 && ip != DIRAC_F32)
+    return set_error(DIRAC_EUNSUPPORTED, "cg_workspace_bytes_eo: inner_prec must be DIRAC_F64 or DIRAC_F32");
+  return layout(hi, ip, true).total;
+}
+
+int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* b, void* x, void* work,
+                int64_t work_bytes, const cg_params* params, cg_stats* stats_out, void* stream) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  Ctx c;
+  cg_params prm;
+  int rc = prepare(op_hi, U_hi, U_lo, b, x, work, work_bytes, params, stats_out, true, "cg_solve_eo", c, prm, stream);
+  if (rc != DIRAC_OK) return rc;
+  const int n = c.hi.nrhs;
+  const double A = c.hi.m_q + 4.0;
+  void* T = c.work + c.L.t;
+  void* EH = c.work + c.L.eh;
+  std::vector<cg_stats> stats(n);
+  for (auto& s : stats) {
+    std::memset(&s, 0, sizeof(s));
+    s.status = DIRAC_ENOCONV;
+  }
+  std::vector<double> bn(n, 0.0), en(n, 0.0), rel(n, std::nan(""));
+  std::vector<bool> fin(n, false);
+
+  // |b| on the full lattice
+  rc = hip_status(norm2(c.hi.g, n, field_of(c.hi, b), c.red(kFinPlain), c.st), "norm");
+  if (rc == DIRAC_OK) rc = c.pull();
+  for (int k = 0; rc == DIRAC_OK && k < n; ++k) {
+    bn[k] = std::sqrt(c.hstate[k].res[0]);
+    if (!std::isfinite(bn[k])) {
+      stats[k].status = DIRAC_EBREAKDOWN;
+      fin[k] = true;
+    } else if (bn[k] == 0.0) {
+      stats[k].status = DIRAC_OK;
+      fin[k] = true;
+    }
+  }
+  // b_hat = b_e - K_eo b_o / A (even plane of T), then eta_hat = D_hat^dag b_hat
+  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, b, b, T, 0, 0, 1.0, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
+  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, T, nullptr, T, 1, 1, 0.0, 1.0, kEpiStore, kGateNone, kFinPlain);
+  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, T, T, EH, 0, 1, A, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
+  if (rc == DIRAC_OK) rc = eta_norms(c, EH, en);
+
+  // The CG stops on the residual of the normal equations; its tolerance
+  // starts below the target (||b - D x|| usually ends a few times above
+  // it) and is tightened, resuming from x, while a source misses the target.
+  double tol_n = 0.25 * prm.tol;
+  for (int pass = 0; rc == DIRAC_OK && pass < 6; ++pass) {
+    std::vector<double> en_pass(n);
+    for (int k = 0; k < n; ++k) en_pass[k] = fin[k] ? 0.0 : en[k];  // 0: nothing left to do
+    cg_params pp = prm;
+    pp.tol = tol_n;
+    rc = solve_with(c, EH, x, pp, en_pass, stats);
+    if (rc != DIRAC_OK) break;
+    // x_o = (b_o - K_oe x_e) / A, then r = b - D x on the full lattice
+    rc = hop(c, c.hi, U_hi, x, b, x, 1, 0, 1.0 / A, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
+    if (rc != DIRAC_OK) break;
+    DslashArgs a = dslash_args(c.hi, U_hi, x, T);
+    rc = run_dslash(DIRAC_F64, DIRAC_F64, c.hi.link, 0, kEpiStore, launch_cfg(c.hi), a, c.st);
+    if (rc != DIRAC_OK) break;
+    const FieldRef TR = field_of(c.hi, T);
+    rc = hip_status(axpby(c.hi.g, n, field_of(c.hi, b), TR, nullptr, 1.0, 0.0, -1.0, 0.0, c.st), "residual");
+    if (rc == DIRAC_OK) rc = hip_status(norm2(c.hi.g, n, TR, c.red(kFinPlain), c.st), "norm");
+    if (rc == DIRAC_OK) rc = c.pull();
+    if (rc != DIRAC_OK) break;
+    double worst = 0.0;
+    bool more = false;
+    for (int k = 0; k < n; ++k) {
+      if (fin[k]) continue;
+      rel[k] = std::sqrt(c.hstate[k].res[0]) / bn[k];
+      stats[k].true_rel_res = rel[k];
+      if (!std::isfinite(rel[k]) || stats[k].status == DIRAC_EBREAKDOWN) {
+        stats[k].status = DIRAC_EBREAKDOWN;
+        fin[k] = true;
+      } else if (rel[k] < prm.tol) {
+        stats[k].status = DIRAC_OK;
+        fin[k] = true;
+      } else if (stats[k].iters >= prm.max_iter) {
+        stats[k].status = DIRAC_ENOCONV;
+        fin[k] = true;
+      } else {
+        stats[k].status = DIRAC_ENOCONV;
+        worst = std::max(worst, rel[k] / prm.tol);
+        more = true;
+      }
+    }
+    if (!more) break;
+    tol_n *= std::min(0.5, std::max(1e-4, 0.5 / worst));
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int overall = DIRAC_OK;
+  for (int k = 0; k < n; ++k) {
+    stats[k].true_rel_res = rel[k];  // the full-lattice residual (a later pass resets finished sources')
+    if (bn[k] == 0.0 && stats[k].status != DIRAC_EBREAKDOWN) {
+      stats[k].status = DIRAC_OK;
+      stats[k].true_rel_res = 0.0;
+    }
+    stats[k].seconds = secs;
+    stats_out[k] = stats[k];
+    if (overall == DIRAC_OK && stats[k].status != DIRAC_OK) overall = stats[k].status;
+  }
+  if (rc != DIRAC_OK) return rc;
+  if (overall != DIRAC_OK)
+    set_error(overall, "cg_solve_eo: not every right-hand side converged (first status %d)", overall);
   return overall;
 }
 

@@ -127,6 +127,14 @@ class Operator:
         abi.check(fn(C.byref(self.op), _ptr(U_int), _ptr(psi_int), _ptr(out), _stream()))
         return out
 
+    def schur(self, U_int, in_int, out=None, dagger=False):
+        """Even-odd Schur complement D_hat (or D_hat^dagger) on the even plane
+        of ``in_int``; the odd plane of ``out`` is overwritten (scratch)."""
+        out = self.empty_spinor(in_int.device) if out is None else out
+        abi.check(self.lib.dirac_schur_apply(C.byref(self.op), _ptr(U_int), _ptr(in_int), _ptr(out),
+                                             1 if dagger else 0, _stream()))
+        return out
+
     def mdagm(self, U_int, psi_int, out=None, tmp=None):
         out = self.empty_spinor(psi_int.device) if out is None else out
         tmp = self.empty_spinor(psi_int.device) if tmp is None else tmp
@@ -185,6 +193,25 @@ def cg(op_hi, U_hi, eta_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec=
     stats = (abi.CgStats * op_hi.nrhs)()
     rc = lib.cg_solve(C.byref(op_hi.op), _ptr(U_hi), _ptr(U_lo), _ptr(eta_int), _ptr(x_int), _ptr(workspace),
                       C.c_int64(workspace.numel()), C.byref(prm), stats, _stream())
+    abi.check(rc, allow=(abi.ENOCONV, abi.EBREAKDOWN) if allow_failure else ())
+    return x_int, [s.as_dict() for s in stats]
+
+
+def cg_eo(op_hi, U_hi, b_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec="f64", U_lo=None,
+          inner_delta=0.0, inner_kmax=0, check_every=0, workspace=None, allow_failure=False):
+    """Solve D x = b through the even-odd Schur complement (cg_solve_eo).
+    Returns (x_int, [stats dict per RHS]); true_rel_res is ||b - D x|| / ||b||."""
+    lib = abi.load()
+    prm = abi.CgParams(float(tol), int(max_iter), _prec(inner_prec), float(inner_delta), int(inner_kmax),
+                       int(check_every))
+    if x_int is None:
+        x_int = torch.zeros_like(b_int)
+    need = int(abi.check(lib.cg_workspace_bytes_eo(C.byref(op_hi.op), C.byref(prm))))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=b_int.device)
+    stats = (abi.CgStats * op_hi.nrhs)()
+    rc = lib.cg_solve_eo(C.byref(op_hi.op), _ptr(U_hi), _ptr(U_lo), _ptr(b_int), _ptr(x_int), _ptr(workspace),
+                         C.c_int64(workspace.numel()), C.byref(prm), stats, _stream())
     abi.check(rc, allow=(abi.ENOCONV, abi.EBREAKDOWN) if allow_failure else ())
     return x_int, [s.as_dict() for s in stats]
 

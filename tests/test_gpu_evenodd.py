@@ -1,0 +1,175 @@
+"""The even-odd (Schur complement) form through the C ABI, against the
+oracle: dirac_schur_apply element by element, and cg_solve_eo (D x = b) by
+its full-lattice residual recomputed by the oracle and by the distance to a
+dense, closed-form or oracle solution."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import evenodd, freefield, lowprec, solvers, wilson
+from paper_1904_08616_amd import _abi as abi
+from paper_1904_08616_amd import dirac as D
+from tests.gpu_helpers import cuda, host, inputs, rel_2, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+# a Vh that is not a multiple of the 128-site block (ragged last tile), one
+# below a single block, and one of several hundred blocks
+SCHUR_DIMS = [((10, 6, 6, 10), "haar"), ((4, 2, 6, 2), "haar"), ((16, 16, 16, 18), "exp")]
+
+
+def _dims(U):
+    lt, lz, ly, lx = U.shape[:4]
+    return (lx, ly, lz, lt)
+
+
+@pytest.mark.parametrize("dims,kind", SCHUR_DIMS)
+@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 18, 5e-6),
+                                           ("f32", 12, 5e-6)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_apply_vs_oracle(dims, kind, prec, link, tol, dagger):
+    U, psi = inputs(dims, kind, seed=3, nrhs=2)
+    m = 0.07
+    op = D.Operator(dims, m, prec, link, 2)
+    Ui = op.pack_gauge(cuda(U))
+    got = host(op.unpack_spinor(op.schur(Ui, op.pack_spinor(cuda(psi)), dagger=dagger)))
+    Ur = lowprec.store_links(U, prec)
+    for k in range(2):
+        ref = evenodd.schur(Ur, lowprec.store(evenodd.restrict(psi[k], 0), prec), m, dagger=dagger)
+        err = rel_inf(evenodd.restrict(got[k], 0), ref)
+        assert err <= tol, (k, err)
+
+
+def test_schur_reads_only_the_even_plane():
+    # NaN on every odd site of the input leaves the even result untouched
+    dims = (8, 4, 6, 8)
+    U, psi = inputs(dims, "haar", seed=4)
+    m = 0.1
+    bad = psi.copy()
+    bad[evenodd.parity(dims) == 1] = np.nan
+    op = D.Operator(dims, m, "f64", 18)
+    Ui = op.pack_gauge(cuda(U))
+    clean = host(op.unpack_spinor(op.schur(Ui, op.pack_spinor(cuda(psi)))))
+    dirty = host(op.unpack_spinor(op.schur(Ui, op.pack_spinor(cuda(bad)))))
+    even = evenodd.parity(dims) == 0
+    assert np.all(np.isfinite(dirty[even]))
+    assert np.array_equal(dirty[even], clean[even])
+
+
+def solve_eo(U, b, m, link=18, inner="f64", tol=1e-10, max_iter=100000, nrhs=1, x0=None, **kw):
+    dims = _dims(U)
+    op = D.Operator(dims, m, "f64", link, nrhs)
+    Ui = op.pack_gauge(cuda(U))
+    Ul = None
+    if inner != "f64":
+        Ul = op.like(prec=inner).pack_gauge(cuda(U))
+    bi = op.pack_spinor(cuda(b))
+    xi = op.pack_spinor(cuda(x0)) if x0 is not None else torch.zeros_like(bi)
+    xi, st = D.cg_eo(op, Ui, bi, xi, tol=tol, max_iter=max_iter, inner_prec=inner, U_lo=Ul, **kw)
+    return host(op.unpack_spinor(xi)), st
+
+
+def d_res(U, b, x, m):
+    return np.linalg.norm((b - wilson.dslash(U, x, m)).ravel()) / np.linalg.norm(b.ravel())
+
+
+def test_solve_4x4x4x4_vs_dense():
+    dims = (4, 4, 4, 4)
+    U, b = inputs(dims, "haar", seed=0)
+    m = 0.1
+    x, st = solve_eo(U, b, m)
+    assert st[0]["status"] == abi.OK, st
+    r = d_res(U, b, x, m)
+    assert r < 1e-10
+    assert abs(st[0]["true_rel_res"] - r) < 1e-12
+    M = wilson.dense_matrix(U, m)
+    xref = wilson.from_vector(np.linalg.solve(M, wilson.to_vector(b)), dims)
+    assert rel_2(x, xref) <= np.linalg.cond(M) * 2e-10
+
+
+@pytest.mark.parametrize("inner,link", [("f64", 18), ("f64", 12), ("f32", 12), ("f32", 18)])
+def test_solve_vs_oracle(inner, link):
+    dims = (8, 8, 8, 16)
+    U, b = inputs(dims, "exp", seed=5)
+    m = 0.02
+    x, st = solve_eo(U, b, m, link=link, inner=inner)
+    assert st[0]["status"] == abi.OK, st
+    r = d_res(U, b, x, m)
+    xo, info = evenodd.solve(U, b, m, tol=1e-12)
+    err = rel_2(x, xo)
+    print(f"eo {inner}/{link} 8^3x16 m=0.02: iters {st[0]['iters']} outer {st[0]['outer']} "
+          f"|b - Dx|/|b| {r:.2e} (reported {st[0]['true_rel_res']:.2e}) err vs oracle {err:.2e} "
+          f"(oracle iters {info['iters']})")
+    assert r < 1e-10
+    assert abs(st[0]["true_rel_res"] - r) <= 0.05 * r
+    # |x - x_ref| <= |D^-1| |b - D x|, and |D^-1| <= 1/m for these links
+    assert err <= (1e-10 + 1e-12) / m * np.linalg.norm(b.ravel()) / np.linalg.norm(xo.ravel())
+
+
+def test_solve_free_field_closed_form():
+    dims = (8, 4, 6, 8)
+    U = synth.links_unit(dims)
+    b = synth.spinor_gauss(dims, synth.rng(6))
+    m = 0.05
+    x, st = solve_eo(U, b, m)
+    assert st[0]["status"] == abi.OK
+    xref = freefield.solve_ddagd(wilson.dslash_dagger(U, b, m), m)
+    assert d_res(U, b, x, m) < 1e-10
+    assert rel_2(x, xref) <= np.sqrt(freefield.condition_number(m)) * 2e-10
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_batched_sources_match_single(inner):
+    # four sources converging at different iterations (one scaled by 1e-3)
+    dims = (8, 4, 4, 8)
+    g = synth.rng(7)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)[:4] + 0.1 * synth.spinor_gauss(dims, g, nrhs=4)
+    src[2] *= 1e-3
+    m = 0.05
+    xb, stb = solve_eo(U, src, m, link=12, inner=inner, nrhs=4)
+    for k in range(4):
+        assert stb[k]["status"] == abi.OK, stb
+        assert d_res(U, src[k], xb[k], m) < 1e-10
+        xs, _ = solve_eo(U, src[k], m, link=12, inner=inner)
+        assert rel_2(xb[k], xs) <= 2e-10 / m
+
+
+def test_fewer_iterations_than_cg_on_normal_equations():
+    dims = (8, 8, 8, 16)
+    U, b = inputs(dims, "exp", seed=8)
+    m = 0.02
+    _, st = solve_eo(U, b, m, link=12)
+    op = D.Operator(dims, m, "f64", 12)
+    Ui = op.pack_gauge(cuda(U))
+    eta = op.apply(Ui, op.pack_spinor(cuda(b)), dagger=True)
+    _, sf = D.cg(op, Ui, eta, tol=1e-10)
+    print(f"iterations: even-odd {st[0]['iters']}, CG on D^dag D {sf[0]['iters']}")
+    assert st[0]["status"] == abi.OK and sf[0]["status"] == abi.OK
+    assert st[0]["iters"] < 0.6 * sf[0]["iters"]
+
+
+def test_failure_paths():
+    dims = (4, 4, 4, 4)
+    U, b = inputs(dims, "haar", seed=9)
+    m = 0.1
+    # iteration cap: ENOCONV after exactly max_iter CG iterations, resumable
+    x1, st = solve_eo(U, b, m, max_iter=3, allow_failure=True)
+    assert st[0]["status"] == abi.ENOCONV and st[0]["iters"] == 3
+    x2, st2 = solve_eo(U, b, m, x0=x1)
+    assert st2[0]["status"] == abi.OK and d_res(U, b, x2, m) < 1e-10
+    # NaN in the source: breakdown, no hang
+    bad = b.copy()
+    bad[1, 2, 3, 0, 2, 1] = np.nan
+    _, st3 = solve_eo(U, bad, m, allow_failure=True)
+    assert st3[0]["status"] == abi.EBREAKDOWN
+    # zero source
+    x4, st4 = solve_eo(U, np.zeros_like(b), m)
+    assert st4[0]["status"] == abi.OK and np.all(x4 == 0)
+    # 16-bit inner formats are not offered here
+    op = D.Operator(dims, m, "f64", 12)
+    with pytest.raises(abi.DiracError):
+        D.cg_eo(op, op.pack_gauge(cuda(U)), op.pack_spinor(cuda(b)), inner_prec="f16s",
+                U_lo=op.like(prec="f16s").pack_gauge(cuda(U)))
