@@ -204,23 +204,23 @@ int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const vo
  * scratch as stated. */
 
 /* out_e = D_hat in_e (dagger = 0) or D_hat^dagger in_e (dagger = 1), for
- * each of op->nrhs fields.  op: DIRAC_F64 or DIRAC_F32 (either link
- * storage).  Only the even plane of `in` is read.  The even plane of `out`
+ * each of op->nrhs fields, in op's format (the 16-bit formats round the
+ * odd intermediate and the result to their storage, as dirac_apply rounds
+ * its output).  Only the even plane of `in` is read.  The even plane of `out`
  * receives the result; its odd plane is overwritten with the intermediate
  * K_oe in_e.  in and out must not overlap (DIRAC_EINVAL).  Asynchronous. */
 int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int, void* out_int, int32_t dagger,
                       void* stream);
 
-/* Bytes of scratch cg_solve_eo needs (params->inner_prec DIRAC_F64 or
- * DIRAC_F32; DIRAC_EUNSUPPORTED otherwise). */
+/* Bytes of scratch cg_solve_eo needs. */
 int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params);
 
 /* Solve D x = b (eq. (1)) for each of op_hi->nrhs sources through the
  * Schur complement:
  *   b_hat = b_e - K_eo b_o / A,
  *   D_hat^dagger D_hat x_e = D_hat^dagger b_hat   (cg_solve's CG: plain
- *       float64 for inner_prec = DIRAC_F64, Algorithm 1 with a float32 inner
- *       solve for DIRAC_F32; the 16-bit formats are not supported here),
+ *       float64 for inner_prec = DIRAC_F64, Algorithm 1 with an inner solve
+ *       in F32, F16S or BF16S otherwise; U_lo as for cg_solve),
  *   x_o = (b_o - K_oe x_e) / A.
  * A source has converged when ||b - D x|| / ||b|| < params->tol, recomputed
  * in float64 on the full lattice after the reconstruction; until then the

@@ -435,7 +435,6 @@ int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int,
   const char* what = "dirac_schur_apply";
   OpInfo o;
   CHECK(check_op(op, &o, what));
-  if (o.prec != DIRAC_F64 && o.prec != DIRAC_F32) return set_error(DIRAC_EUNSUPPORTED, "%s: F64 or F32 only", what);
   CHECK(check_ptr(U_int, "U_int", what));
   CHECK(check_ptr(in_int, "in_int", what));
   CHECK(check_ptr(out_int, "out_int", what));

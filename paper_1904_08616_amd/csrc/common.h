@@ -28,10 +28,12 @@ struct Geom {
   int Vh;  // sites per parity
   int sZ;  // checkerboard stride of z: Xh * Y
   int sT;  // checkerboard stride of t: Xh * Y * Z
+  int vpar;  // site-wise field operations: -1 both parities, 0 / 1 that parity only
 };
 
 inline Geom make_geom(const int L[4]) {
   Geom g;
+  g.vpar = -1;
   g.X = L[0]; g.Y = L[1]; g.Z = L[2]; g.T = L[3];
   g.Xh = g.X / 2;
   g.sZ = g.Xh * g.Y;

@@ -13,14 +13,17 @@ namespace {
 constexpr int kBlock = 256;
 
 struct SiteGrid {
-  int nb;  // blocks per parity
+  int nb;      // blocks per parity
+  int nparts;  // blocks per right-hand side (reduction partials)
   dim3 grid;
 };
 
+// Both parities, or only parity g.vpar (the even-odd solve's half vectors).
 SiteGrid site_grid(const Geom& g, int nrhs) {
   SiteGrid s;
   s.nb = (g.Vh + kBlock - 1) / kBlock;
-  s.grid = dim3(2 * s.nb, nrhs);
+  s.nparts = (g.vpar < 0 ? 2 : 1) * s.nb;
+  s.grid = dim3(s.nparts, nrhs);
   return s;
 }
 
@@ -31,8 +34,13 @@ struct SiteIdx {
 
 __device__ __forceinline__ SiteIdx site_idx(const Geom& g, int nb) {
   SiteIdx s;
-  s.p = blockIdx.x >= (unsigned)nb ? 1 : 0;
-  s.i = (blockIdx.x - s.p * nb) * kBlock + threadIdx.x;
+  if (g.vpar >= 0) {
+    s.p = g.vpar;
+    s.i = blockIdx.x * kBlock + threadIdx.x;
+  } else {
+    s.p = blockIdx.x >= (unsigned)nb ? 1 : 0;
+    s.i = (blockIdx.x - s.p * nb) * kBlock + threadIdx.x;
+  }
   s.rhs = blockIdx.y;
   s.valid = s.i < g.Vh;
   return s;
@@ -135,7 +143,8 @@ __device__ __forceinline__ void site_reduce(const RedArgs& ra, double (&v)[NC], 
   double vals[1][NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) vals[0][c] = v[c];
-  block_reduce_store<1, NC>(ra, vals, blockIdx.y, nrhs, blockIdx.x, 2 * nb);
+  (void)nb;
+  block_reduce_store<1, NC>(ra, vals, blockIdx.y, nrhs, blockIdx.x, gridDim.x);
 }
 
 RedArgs red_args(const RedTarget& t) { return RedArgs{t.partials, t.state, t.kind}; }
@@ -448,7 +457,7 @@ static hipError_t convert_from(const Geom& g, int nrhs, FieldRef src, FieldRef d
                                              sg.nb, nrhs, dev(src), dev(dst), cs, ci, ra));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize(ra, 2 * sg.nb, nrhs, 1, st);
+    return launch_finalize(ra, sg.nparts, nrhs, 1, st);
   } else {
     PREC_SWITCH(dst.prec, hipLaunchKernelGGL((k_convert<PS, P_, false>), sg.grid, dim3(kBlock), 0, st, g,
                                              sg.nb, nrhs, dev(src), dev(dst), cs, ci, ra));
@@ -475,7 +484,7 @@ static hipError_t dot_from(const Geom& g, int nrhs, FieldRef a, FieldRef b, cons
                                          dev(a), dev(b), red_args(red)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(red_args(red), 2 * sg.nb, nrhs, 2, st);
+  return launch_finalize(red_args(red), sg.nparts, nrhs, 2, st);
 }
 
 hipError_t dot(const Geom& g, int nrhs, FieldRef a, FieldRef b, const RedTarget& red, hipStream_t st) {
@@ -494,7 +503,7 @@ hipError_t norm2(const Geom& g, int nrhs, FieldRef a, const RedTarget& red, hipS
                                          dev(a), red_args(red)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(red_args(red), 2 * sg.nb, nrhs, 1, st);
+  return launch_finalize(red_args(red), sg.nparts, nrhs, 1, st);
 }
 
 template <int PX>

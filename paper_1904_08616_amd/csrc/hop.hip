@@ -14,7 +14,8 @@
 // layout; a launch touches only the plane of its output parity, so one
 // buffer can hold an even vector and the odd intermediate of the same
 // operator.  Epilogues as in the full stencil: store, store plus |out|^2, or
-// dst = src - alpha out plus |dst|^2.
+// dst = src - alpha out plus |dst|^2 (dst in float32 for the scaled 16-bit
+// formats).
 //
 // One thread per output site and right-hand side (the per-site stencil's
 // hop code); the grid covers one parity only.
@@ -26,11 +27,13 @@ namespace {
 
 constexpr int kHopBlock = 128;
 
-template <int P, int LK, bool DAG, int EPI>
-__global__ void __launch_bounds__(kHopBlock) __attribute__((amdgpu_waves_per_eu(dslash_waves<P, 1>())))
+template <int PI, int PO, int LK, bool DAG, int EPI>
+__global__ void __launch_bounds__(kHopBlock) __attribute__((amdgpu_waves_per_eu(dslash_waves<PI, 1>())))
 k_hop(DslashArgs a) {
-  using SF = SpinFmt<P>;
-  using Rl = typename SF::R;
+  using SI = SpinFmt<PI>;
+  using SO = SpinFmt<PO>;
+  using Rl = typename SI::R;
+  using Ro = typename SO::R;
   const int Vh = a.g.Vh;
   const int l = xcd_tile(blockIdx.x, a.ntiles * a.ngroups, a.remap);
   const int rhs = l % a.ngroups;  // right-hand sides of one tile side by side
@@ -49,37 +52,43 @@ k_hop(DslashArgs a) {
     Cx<Rl> acc[1][12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[0][k] = {Rl(0), Rl(0)};
-    hop_dir<P, LK, DAG, 1, 0>(a, Ur, in, c, p, i, onr, acc);
-    hop_dir<P, LK, DAG, 1, 1>(a, Ur, in, c, p, i, onr, acc);
-    hop_dir<P, LK, DAG, 1, 2>(a, Ur, in, c, p, i, onr, acc);
-    hop_dir<P, LK, DAG, 1, 3>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<PI, LK, DAG, 1, 0>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<PI, LK, DAG, 1, 1>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<PI, LK, DAG, 1, 2>(a, Ur, in, c, p, i, onr, acc);
+    hop_dir<PI, LK, DAG, 1, 3>(a, Ur, in, c, p, i, onr, acc);
 
     const Rl ch = (Rl)(0.5 * a.hop_c);
-    Cx<Rl> o[12];
+    Cx<Ro> o[12];
     if (a.ctr != nullptr) {
       Cx<Rl> v[12];
-      SF::load(make_rsrc(a.ctr + (size_t)rhs * a.ctr_stride, a.field_bytes), Vh, p, i, v);
+      SI::load(make_rsrc(a.ctr + (size_t)rhs * a.ctr_stride, a.field_bytes), Vh, p, i, v);
       const Rl cm = (Rl)a.mass4;
 #pragma unroll
       for (int k = 0; k < 12; ++k)
-        o[k] = {fma(cm, v[k].re, ch * acc[0][k].re), fma(cm, v[k].im, ch * acc[0][k].im)};
+        o[k] = {(Ro)fma(cm, v[k].re, ch * acc[0][k].re), (Ro)fma(cm, v[k].im, ch * acc[0][k].im)};
     } else {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) o[k] = {ch * acc[0][k].re, ch * acc[0][k].im};
+      for (int k = 0; k < 12; ++k) o[k] = {(Ro)(ch * acc[0][k].re), (Ro)(ch * acc[0][k].im)};
     }
     if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
       const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
-      SF::store(orsrc, Vh, p, i, o);
+      SO::store(orsrc, Vh, p, i, o);
       if constexpr (EPI == kEpiStoreNorm) {
+        // the exact result paired with the value as stored, as in the full
+        // stencil (the two differ for the scaled 16-bit formats)
+        Cx<Ro> q[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q[k] = o[k];
+        SO::round(q);
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) s += (double)o[k].re * o[k].re + (double)o[k].im * o[k].im;
+        for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
         vals[0][0] = s;
       }
     } else {
-      const Rl cf = a.sub_alpha ? (Rl)a.red.state[rhs].alpha : Rl(1);
-      Cx<Rl> d[12];
-      SF::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
+      const Ro cf = a.sub_alpha ? (Ro)a.red.state[rhs].alpha : Ro(1);
+      Cx<Ro> d[12];
+      SO::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
       double s = 0.0;
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
@@ -87,33 +96,36 @@ k_hop(DslashArgs a) {
         d[k].im = fma(-cf, o[k].im, d[k].im);
         s += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
       }
-      SF::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, d);
+      SO::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, d);
       vals[0][0] = s;
     }
   }
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, tile, a.ntiles);
 }
 
-template <int P, int LK, bool DAG, int EPI>
+template <int PI, int PO, int LK, bool DAG, int EPI>
 hipError_t launch_hop(DslashArgs a, hipStream_t st) {
   a.ngroups = a.nrhs;
   a.ntiles = (a.g.Vh + kHopBlock - 1) / kHopBlock;
-  hipLaunchKernelGGL((k_hop<P, LK, DAG, EPI>), dim3(a.ntiles * a.ngroups), dim3(kHopBlock), 0, st, a);
+  hipLaunchKernelGGL((k_hop<PI, PO, LK, DAG, EPI>), dim3(a.ntiles * a.ngroups), dim3(kHopBlock), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || EPI == kEpiStore) return e;
   return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);
 }
 
+// The residual update of a scaled 16-bit operator writes float32 (as in the
+// full stencil); everything else keeps the input format.
 template <int P, int LK>
 hipError_t hop_dispatch(int dag, int epi, const DslashArgs& a, hipStream_t st) {
+  constexpr int PS = (P == DIRAC_F16S || P == DIRAC_BF16S) ? DIRAC_F32 : P;
   if (dag) {
-    if (epi == kEpiStore) return launch_hop<P, LK, true, kEpiStore>(a, st);
-    if (epi == kEpiStoreNorm) return launch_hop<P, LK, true, kEpiStoreNorm>(a, st);
-    return launch_hop<P, LK, true, kEpiSubNorm>(a, st);
+    if (epi == kEpiStore) return launch_hop<P, P, LK, true, kEpiStore>(a, st);
+    if (epi == kEpiStoreNorm) return launch_hop<P, P, LK, true, kEpiStoreNorm>(a, st);
+    return launch_hop<P, PS, LK, true, kEpiSubNorm>(a, st);
   }
-  if (epi == kEpiStore) return launch_hop<P, LK, false, kEpiStore>(a, st);
-  if (epi == kEpiStoreNorm) return launch_hop<P, LK, false, kEpiStoreNorm>(a, st);
-  return launch_hop<P, LK, false, kEpiSubNorm>(a, st);
+  if (epi == kEpiStore) return launch_hop<P, P, LK, false, kEpiStore>(a, st);
+  if (epi == kEpiStoreNorm) return launch_hop<P, P, LK, false, kEpiStoreNorm>(a, st);
+  return launch_hop<P, PS, LK, false, kEpiSubNorm>(a, st);
 }
 
 }  // namespace
@@ -130,7 +142,9 @@ int run_hop(int prec, int link, int dag, int epi, DslashArgs a, hipStream_t st) 
   else if (prec == DIRAC_F64 && link == 12) e = hop_dispatch<DIRAC_F64, 12>(dag, epi, a, st);
   else if (prec == DIRAC_F32 && link == 18) e = hop_dispatch<DIRAC_F32, 18>(dag, epi, a, st);
   else if (prec == DIRAC_F32 && link == 12) e = hop_dispatch<DIRAC_F32, 12>(dag, epi, a, st);
-  else return set_error(DIRAC_EUNSUPPORTED, "half-lattice hop: F64 or F32 only (prec %d link %d)", prec, link);
+  else if (prec == DIRAC_F16S && link == 12) e = hop_dispatch<DIRAC_F16S, 12>(dag, epi, a, st);
+  else if (prec == DIRAC_BF16S && link == 12) e = hop_dispatch<DIRAC_BF16S, 12>(dag, epi, a, st);
+  else return set_error(DIRAC_EUNSUPPORTED, "half-lattice hop: no kernel for prec %d link %d", prec, link);
   return hip_status(e, "half-lattice hop launch");
 }
 

@@ -33,11 +33,10 @@
 // equations of the even-site Schur complement, D_hat^dagger D_hat x_e =
 // D_hat^dagger b_hat, for the system D x = b: the two operator applications
 // of an iteration become two half-lattice hops each, and the vector
-// operations act on the even planes of the fields only (the even plane of a
-// field, read as a field of half as many sites, has the same elementwise
-// structure).  The odd sites are reconstructed afterwards and the residual
-// ||b - D x|| checked on the full lattice; if it is still above the target,
-// the CG tolerance is tightened and the solve resumed from the current x.
+// operations act on the even sites of the fields only.  The odd sites are
+// reconstructed afterwards and the residual ||b - D x|| checked on the full
+// lattice; if it is still above the target, the CG tolerance is tightened
+// and the solve resumed from the current x.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,7 +90,7 @@ Layout layout(const OpInfo& hi, int inner_prec, bool eo = false) {
 struct Ctx {
   OpInfo hi, lo;
   bool eo = false;  // operator: D_hat of the even-odd form instead of D
-  Geom vg;          // geometry of the vector operations (even planes only when eo)
+  Geom vg;          // geometry of the vector operations (even sites only when eo)
   const void* Uhi;
   const void* Ulo;
   char* work;
@@ -123,10 +122,11 @@ RedArgs to_args(const RedTarget& t) { return RedArgs{t.partials, t.state, t.kind
 double norm_of(double v) { return std::isnan(v) ? v : std::sqrt(v > 0.0 ? v : 0.0); }
 
 // Half-lattice hop: on the sites of parity par, out = cm * ctr + ch * K in
-// (K of D^dagger when dag), with epilogue epi; src and use_alpha for the
-// subtraction epilogue.
+// (K of D^dagger when dag), with epilogue epi; src, use_alpha and the format
+// of src / out (oprec, when it differs from o's) for the subtraction epilogue.
 int hop(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void* ctr, void* out, int par,
-        int dag, double cm, double ch, int epi, int gate, int kind, const void* src = nullptr, int use_alpha = 0) {
+        int dag, double cm, double ch, int epi, int gate, int kind, const void* src = nullptr, int use_alpha = 0,
+        int oprec = -1) {
   DslashArgs a = dslash_args(o, U, in, out);
   a.par = par;
   a.ctr = (const char*)ctr;
@@ -138,6 +138,12 @@ int hop(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void
   a.src = (const char*)src;
   a.src_stride = o.field_stride;
   a.sub_alpha = use_alpha;
+  if (oprec >= 0 && oprec != o.prec) {
+    const FieldRef d = field_as(c.hi, oprec, out);
+    a.out_bytes = d.bytes;
+    a.out_stride = d.stride;
+    a.src_stride = d.stride;
+  }
   return run_hop(o.prec, o.link, dag, epi, a, c.st);
 }
 
@@ -162,11 +168,12 @@ int dslash_norm(const Ctx& c, const OpInfo& o, const void* U, const void* in, vo
 int dslash_sub(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void* src, void* dst, int dprec,
                int use_alpha, int gate, int kind) {
   if (c.eo) {
-    if (dprec != o.prec) return set_error(DIRAC_EUNSUPPORTED, "even-odd residual update: mixed formats");
+    const int want = (o.prec == DIRAC_F16S || o.prec == DIRAC_BF16S) ? DIRAC_F32 : o.prec;
+    if (dprec != want) return set_error(DIRAC_EUNSUPPORTED, "even-odd residual update: format %d", dprec);
     const double A = o.m_q + 4.0;
     int rc = hop(c, o, U, in, nullptr, (void*)in, 1, 1, 0.0, 1.0, kEpiStore, gate, kFinPlain);
     if (rc != DIRAC_OK) return rc;
-    return hop(c, o, U, in, in, dst, 0, 1, A, -1.0 / A, kEpiSubNorm, gate, kind, src, use_alpha);
+    return hop(c, o, U, in, in, dst, 0, 1, A, -1.0 / A, kEpiSubNorm, gate, kind, src, use_alpha, dprec);
   }
   DslashArgs a = dslash_args(o, U, in, dst);
   const FieldRef d = field_as(c.hi, dprec, dst);
@@ -468,8 +475,6 @@ int prepare(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const voi
   const int ip = prm.inner_prec;
   if (ip != DIRAC_F64 && ip != DIRAC_F32 && ip != DIRAC_F16S && ip != DIRAC_BF16S)
     return set_error(DIRAC_EINVAL, "%s: unknown inner_prec %d", what, ip);
-  if (eo && ip != DIRAC_F64 && ip != DIRAC_F32)
-    return set_error(DIRAC_EUNSUPPORTED, "%s: inner_prec must be DIRAC_F64 or DIRAC_F32", what);
   if (!U_hi || !eta || !x || !work) return set_error(DIRAC_EINVAL, "%s: NULL buffer", what);
   if (ip != DIRAC_F64 && !U_lo) return set_error(DIRAC_EINVAL, "%s: U_lo is NULL for a mixed solve", what);
   if ((((uintptr_t)U_hi | (uintptr_t)eta | (uintptr_t)x | (uintptr_t)work | (uintptr_t)U_lo) & 255u) != 0)
@@ -492,7 +497,7 @@ int prepare(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const voi
   c.lo = hi;
   c.eo = eo;
   c.vg = hi.g;
-  if (eo) c.vg.Vh = hi.g.Vh / 2;  // the even plane as a field of V/2 sites (V is a multiple of 16)
+  if (eo) c.vg.vpar = 0;  // vector operations on the even sites only
   if (ip != DIRAC_F64) {
     dirac_op lo = *op_hi;
     lo.prec = ip;
@@ -594,8 +599,8 @@ int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params) {
   if (rc != DIRAC_OK) return rc;
   if (params == nullptr) return set_error(DIRAC_EINVAL, "cg_workspace_bytes_eo: params is NULL");
   const int ip = params->inner_prec;
-  if (ip != DIRAC_F64 && ip != DIRAC_F32)
-    return set_error(DIRAC_EUNSUPPORTED, "cg_workspace_bytes_eo: inner_prec must be DIRAC_F64 or DIRAC_F32");
+  if (ip != DIRAC_F64 && ip != DIRAC_F32 && ip != DIRAC_F16S && ip != DIRAC_BF16S)
+    return set_error(DIRAC_EINVAL, "cg_workspace_bytes_eo: unknown inner_prec %d", ip);
   return layout(hi, ip, true).total;
 }
 
