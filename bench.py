@@ -11,7 +11,10 @@ spinor read + one spinor written (960 B in float64, 18-real).
 The same line carries the roofline of that kernel (HIP events on the launch
 stream), the CPU oracle timed on a bounded sample of the same workload, and
 "extra" results: 12-real links, the HBM-bound 32^3 x 64 lattice in every
-precision, and CG time-to-1e-10 (float64 vs Algorithm 1 mixed precision).
+precision, CG time-to-1e-10 (float64 vs Algorithm 1 mixed precision), the
+12-source and multi-lattice batches, the link force, BLAS-1, and the solve
+of D x = b through the even-odd Schur complement against CG on the normal
+equations of D.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 """
@@ -225,6 +228,77 @@ def cg_time_multi(torch, D, dims, U, src, m_q, inner, link=12, tol=1e-10):
             "all_converged": all(s["status"] == 0 for s in st)}
 
 
+def schur_bytes(prec, link):
+    """Compulsory bytes per lattice site of one even-odd Schur application
+    D_hat = A - K_eo K_oe / A (two half-lattice hops): each hop reads every
+    link once, a half-lattice input and writes a half-lattice output; the
+    second also reads the half-lattice centre."""
+    link_b = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[prec] * link * 4
+    half = {"f64": 192, "f32": 96, "f16s": 52, "bf16s": 52}[prec] / 2
+    return 2 * link_b + 5 * half
+
+
+def time_schur(torch, D, dims, prec, link, U, psi, steps, m_q):
+    """Average ms of one D_hat application (rotating input copies past the
+    last-level cache)."""
+    op = D.Operator(dims, m_q, prec, link)
+    Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    pi = op.pack_spinor(torch.from_numpy(psi).cuda())
+    per_set = op.gauge_bytes() + 2 * op.spinor_bytes()
+    copies = max(1, min(8, math.ceil(2 * LLC_BYTES / per_set) + 1))
+    sets = [(Ui, pi, op.empty_spinor())] + [(Ui.clone(), pi.clone(), op.empty_spinor()) for _ in range(copies - 1)]
+    for k in range(5):
+        u, p, c = sets[k % copies]
+        op.schur(u, p, out=c)
+    with Timer(torch) as t:
+        for k in range(steps):
+            u, p, c = sets[k % copies]
+            op.schur(u, p, out=c)
+    ms = t.ms / steps
+    b = schur_bytes(prec, link) * int(np.prod(dims))
+    return {"ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
+            "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def _d_residuals(torch, op, Ui, b_int, x_int):
+    """||b - D x|| / ||b|| per right-hand side (float64 internal fields)."""
+    r = (b_int.view(torch.float64) - op.apply(Ui, x_int).view(torch.float64)).reshape(op.nrhs, -1)
+    nb = torch.linalg.vector_norm(b_int.view(torch.float64).reshape(op.nrhs, -1), dim=1)
+    return (torch.linalg.vector_norm(r, dim=1) / nb).tolist()
+
+
+def solve_d_time(torch, D, dims, U, b, m_q, method, link=12, tol=1e-10):
+    """Time to solve D x = b for all sources of b ([nrhs, ...] or one field):
+    method "eo_<inner>" is the even-odd Schur solve, "ddagd_<inner>" the CG on
+    D^dag D x = D^dag b; the residual ||b - D x|| / ||b|| is recomputed after
+    the solve.  One untimed solve first (tuning, first touch)."""
+    kind, inner = method.split("_")
+    nrhs = b.shape[0] if b.ndim == 7 else 1
+    op = D.Operator(dims, m_q, "f64", link, nrhs)
+    Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    bi = op.pack_spinor(torch.from_numpy(b).cuda())
+    tune_for_solve(op, Ui, bi)
+    Ul = None
+    if inner != "f64":
+        lo = op.like(prec=inner, link=link if inner == "f32" else 12)
+        Ul = lo.pack_gauge(torch.from_numpy(U).cuda())
+        tune_for_solve(lo, Ul, lo.pack_spinor(torch.from_numpy(b).cuda()))
+
+    def run():
+        x = torch.zeros_like(bi)
+        if kind == "eo":
+            return D.cg_eo(op, Ui, bi, x, tol=tol, inner_prec=inner, U_lo=Ul)
+        eta = op.apply(Ui, bi, dagger=True)
+        return D.cg(op, Ui, eta, x, tol=tol, inner_prec=inner, U_lo=Ul)
+
+    run()
+    with Timer(torch) as t:
+        x, st = run()
+    res = _d_residuals(torch, op, Ui, bi, x)
+    return {"ms": round(t.ms, 2), "iters_max": max(s["iters"] for s in st),
+            "d_rel_res_max": max(res), "all_status_ok": all(s["status"] == 0 for s in st)}
+
+
 def bench_multi_rhs(torch, D, steps, warmup):
     """12 point sources (one per spin x colour) on 24^3 x 48, float32 with
     12-real links: one 12-RHS Dslash against twelve single ones, and the
@@ -256,6 +330,10 @@ def bench_multi_rhs(torch, D, steps, warmup):
         iters.append(r["iters"])
     out["cg_24x24x24x48_m0.05_12_point_sources"]["sequential_f64_ms"] = round(seq, 2)
     out["cg_24x24x24x48_m0.05_12_point_sources"]["sequential_f64_iters_max"] = max(iters)
+    # the propagator D x = b for the 12 sources: even-odd Schur solves against
+    # CG on the normal equations of D (batched, all sources at once)
+    out["solve_Dx=b_24x24x24x48_m0.05_12_point_sources"] = {
+        m: solve_d_time(torch, D, dims, U, src, 0.05, m) for m in ("ddagd_f32", "eo_f64", "eo_f32", "eo_f16s")}
     return out
 
 
@@ -425,6 +503,9 @@ def main(argv=None):
     ap.add_argument("--profile-cg", action="store_true",
                     help="only the 32^3x64 CG solves (float64, F32 and F16S inner), one JSON line; "
                          "for kernel traces of the solver (run after a full bench with DIRAC_TUNE_CACHE set)")
+    ap.add_argument("--profile-eo", action="store_true",
+                    help="only the even-odd Schur operator and the 32^3x64 solves of D x = b (float64 and F16S "
+                         "inner), one JSON line; for kernel traces of the half-lattice hops")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); "
@@ -441,6 +522,15 @@ def main(argv=None):
         Ub, pb = gen_inputs(big, seed=0)
         res = {inner: cg_time(torch, D, big, Ub, pb, 0.02, inner, link=12) for inner in ("f64", "f32", "f16s")}
         print(json.dumps({"cg_32x32x32x64_m0.02_link12": res}), flush=True)
+        return 0
+    if a.profile_eo:
+        big = (32, 32, 32, 64)
+        log("generating 32^3x64 inputs")
+        Ub, pb = gen_inputs(big, seed=0)
+        res = {f"schur_{prec}_link12": time_schur(torch, D, big, prec, 12, Ub, pb, 50, 0.02)
+               for prec in ("f64", "f16s")}
+        res.update({m: solve_d_time(torch, D, big, Ub, pb, 0.02, m) for m in ("eo_f64", "eo_f16s")})
+        print(json.dumps({"evenodd_32x32x32x64_m0.02": res}), flush=True)
         return 0
     dims = (16, 16, 16, 32)
     V = int(np.prod(dims))
@@ -542,6 +632,13 @@ def main(argv=None):
             for inner, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
                 extra[f"cg_32x32x32x64_m0.02_{inner}_link{link}"] = cg_time(torch, D, big, Ub, pb, 0.02, inner,
                                                                             link=link)
+            log("even-odd 32^3x64: Schur operator and the solve of D x = b")
+            for prec in ("f64", "f16s"):
+                extra[f"schur_32x32x32x64_{prec}_link12"] = time_schur(torch, D, big, prec, 12, Ub, pb,
+                                                                       max(20, a.steps // 8), 0.02)
+            extra["solve_Dx=b_32x32x32x64_m0.02_link12"] = {
+                m: solve_d_time(torch, D, big, Ub, pb, 0.02, m)
+                for m in ("ddagd_f64", "ddagd_f16s", "eo_f64", "eo_f32", "eo_f16s")}
             del Ub, pb
             torch.cuda.empty_cache()
             log("multi-RHS 24^3x48")

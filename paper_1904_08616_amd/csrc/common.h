@@ -339,38 +339,47 @@ template <bool BF> struct SpinScaled {
         v[4 * k + j] = {s * dec((unsigned short)(w[j] & 0xFFFFu)), s * dec((unsigned short)(w[j] >> 16))};
     }
   }
-  // Site maximum |v| and its reciprocal (0 for an all-zero site).  The
-  // quotients are formed as v * (1/m): within one float ulp of v / m, and
-  // the site maximum still rounds to exactly +-1 in the 16-bit format; one
-  // division per site instead of 24.
+  // Site maximum |v|.
   __device__ static __forceinline__ float site_max(const Cx<R> (&v)[12]) {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
     return m;
   }
+  // The payload v / m is formed as (v * pre) * inv: one division per site
+  // instead of 24, within one float ulp of v / m, and the site maximum still
+  // rounds to exactly +-1 in the 16-bit format.  pre = 1 and inv = 1 / m,
+  // except for a denormal m (a site far out on the tail of a point-source
+  // solve), whose reciprocal would overflow: there pre = 2^64 and
+  // inv = 1 / (m 2^64), both scalings exact.  An all-zero site has inv = 0.
+  __device__ static __forceinline__ void site_factors(float m, float& pre, float& inv) {
+    pre = (m < 0x1p-126f) ? 0x1p64f : 1.f;
+    inv = (m > 0.f) ? 1.f / (m * pre) : 0.f;
+  }
   // Replace v by the value the store would leave in memory.
   __device__ static __forceinline__ void round(Cx<R> (&v)[12]) {
     const float m = site_max(v);
-    const float inv = (m > 0.f) ? 1.f / m : 0.f;
+    float pre, inv;
+    site_factors(m, pre, inv);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      v[c].re = m * dec(enc(v[c].re * inv));
-      v[c].im = m * dec(enc(v[c].im * inv));
+      v[c].re = m * dec(enc((v[c].re * pre) * inv));
+      v[c].im = m * dec(enc((v[c].im * pre) * inv));
     }
   }
   template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
     const float m = site_max(v);
-    const float inv = (m > 0.f) ? 1.f / m : 0.f;
+    float pre, inv;
+    site_factors(m, pre, inv);
     const uint32_t o = (uint32_t)i * 16u + plane_off(p, 3u * (uint32_t)Vh * 16u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       unsigned w[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float re = v[4 * k + j].re * inv;
-        const float im = v[4 * k + j].im * inv;
+        const float re = (v[4 * k + j].re * pre) * inv;
+        const float im = (v[4 * k + j].im * pre) * inv;
         w[j] = (unsigned)enc(re) | ((unsigned)enc(im) << 16);
       }
       bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));

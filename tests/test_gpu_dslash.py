@@ -270,3 +270,29 @@ def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
         assert op.launch_config()["lds"] == 1
         got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
         assert rel_inf(got, ref) <= tol, (remap,)
+
+
+@pytest.mark.parametrize("prec,eps", [("f16s", 2.0 ** -11), ("bf16s", 2.0 ** -8)])
+def test_scaled_formats_tiny_site_maxima(prec, eps):
+    # sites whose largest component is a float32 denormal (down to 1e-44),
+    # just around the smallest normal float, and ordinary ones: the reciprocal
+    # of a denormal maximum overflows a float, so the store must not form it
+    dims = (4, 2, 2, 4)
+    g = synth.rng(22)
+    v = synth.spinor_gauss(dims, g)
+    mags = np.array([1e-44, 1e-40, 1e-39, 1.1e-38, 1.2e-38, 1e-30, 1.0, 1e3])
+    V = int(np.prod(dims))
+    site = mags[np.arange(V) % len(mags)].reshape(dims[::-1])
+    vmax = np.maximum(np.abs(v.real), np.abs(v.imag)).max(axis=(-1, -2))
+    v = v * (site / vmax)[..., None, None]
+    op = D.Operator(dims, 0.1, "f64", 12)
+    lo = op.like(prec=prec)
+    got = host(lo.unpack_spinor(op.convert(op.pack_spinor(cuda(v)), lo)))
+    assert np.all(np.isfinite(got))
+    s = lowprec.site_scale(v)[..., None, None]
+    # format rounding relative to the site scale, plus the float32 rounding
+    # of denormal components on the way in (at most half of 2^-149)
+    bound = eps * s * 1.0001 + 2.0 ** -150
+    assert np.all(np.abs((got - v).real) <= bound) and np.all(np.abs((got - v).imag) <= bound)
+    ref = lowprec.store(v, prec)
+    assert np.all(np.abs((got - ref).real) <= 2 * bound) and np.all(np.abs((got - ref).imag) <= 2 * bound)

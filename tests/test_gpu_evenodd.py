@@ -188,3 +188,26 @@ def test_failure_paths():
     op = D.Operator(dims, m, "f64", 12)
     with pytest.raises(abi.DiracError):
         D.cg_eo(op, op.pack_gauge(cuda(U)), op.pack_spinor(cuda(b)), inner_prec="f16s", U_lo=None)
+
+
+def test_point_source_16bit_inner_solves_do_the_work():
+    # 24^3 x 48 point source (the 12-source workload's first source): far
+    # from the source, vector sites with a float32-denormal maximum appear;
+    # their scaled 16-bit store once overflowed, and every inner cycle broke
+    # down until the solve fell back to float64.  Both the even-odd solve and
+    # CG on the normal equations must now run in the inner format.
+    dims = (24, 24, 24, 48)
+    g = synth.rng(0)
+    U = synth.links_exp(dims, 0.3, g)
+    b = synth.point_sources(dims)[0]
+    m = 0.05
+    x, st = solve_eo(U, b, m, link=12, inner="f16s")
+    assert st[0]["status"] == abi.OK, st
+    assert st[0]["dslash_hi"] <= 4 * st[0]["outer"] + 4, st
+    assert d_res(U, b, x, m) < 1e-10
+    op = D.Operator(dims, m, "f64", 12)
+    Ui = op.pack_gauge(cuda(U))
+    eta = op.apply(Ui, op.pack_spinor(cuda(b)), dagger=True)
+    _, sf = D.cg(op, Ui, eta, tol=1e-10, inner_prec="f16s", U_lo=op.like(prec="f16s").pack_gauge(cuda(U)))
+    assert sf[0]["status"] == abi.OK
+    assert sf[0]["dslash_hi"] <= 4 * sf[0]["outer"] + 4, sf
