@@ -267,6 +267,28 @@ def _d_residuals(torch, op, Ui, b_int, x_int):
     return (torch.linalg.vector_norm(r, dim=1) / nb).tolist()
 
 
+def small_cg_time(torch, D):
+    """CG on D^dag D to 1e-10 on 4^4 (Haar links, seed 0, m_q = 0.1): the
+    iterations in a single launch against the multi-kernel iteration."""
+    import synth
+    dims = (4, 4, 4, 4)
+    g = synth.rng(0)
+    U = synth.links_haar(dims, g)
+    eta = synth.spinor_gauss(dims, g)
+    op = D.Operator(dims, 0.1, "f64", 18)
+    Ui = op.pack_gauge(torch.from_numpy(U).cuda())
+    e = op.pack_spinor(torch.from_numpy(eta).cuda())
+    out = {}
+    for name, sl in (("single_launch", 1), ("multi_kernel", -1)):
+        best = None
+        for _ in range(4):
+            with Timer(torch) as t:
+                _, st = D.cg(op, Ui, e, tol=1e-10, single_launch=sl)
+            best = t.ms if best is None else min(best, t.ms)
+        out[name] = {"ms": round(best, 3), "iters": st[0]["iters"], "true_rel_res": st[0]["true_rel_res"]}
+    return out
+
+
 def solve_d_time(torch, D, dims, U, b, m_q, method, link=12, tol=1e-10):
     """Time to solve D x = b for all sources of b ([nrhs, ...] or one field):
     method "eo_<inner>" is the even-odd Schur solve, "ddagd_<inner>" the CG on
@@ -277,12 +299,14 @@ def solve_d_time(torch, D, dims, U, b, m_q, method, link=12, tol=1e-10):
     op = D.Operator(dims, m_q, "f64", link, nrhs)
     Ui = op.pack_gauge(torch.from_numpy(U).cuda())
     bi = op.pack_spinor(torch.from_numpy(b).cuda())
-    tune_for_solve(op, Ui, bi)
     Ul = None
     if inner != "f64":
         lo = op.like(prec=inner, link=link if inner == "f32" else 12)
         Ul = lo.pack_gauge(torch.from_numpy(U).cuda())
-        tune_for_solve(lo, Ul, lo.pack_spinor(torch.from_numpy(b).cuda()))
+    if kind == "ddagd":  # the even-odd solve runs the half-lattice hops, which take no tuning
+        tune_for_solve(op, Ui, bi)
+        if inner != "f64":
+            tune_for_solve(lo, Ul, lo.pack_spinor(torch.from_numpy(b).cuda()))
 
     def run():
         x = torch.zeros_like(bi)
@@ -610,6 +634,8 @@ def main(argv=None):
             extra["dslash_16x16x16x32_f64_link12"] = {
                 "ms": round(ms12, 5), "GB/s": round(b12 / (ms12 * 1e-3) / 1e9, 1),
                 "frac": round(b12 / (ms12 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launch": cfg12}
+            log("CG 4^4: the single-launch iteration against the multi-kernel one")
+            extra["cg_4x4x4x4_m0.1_f64_link18"] = small_cg_time(torch, D)
             log("CG 16^3x32 float64 vs mixed")
             eta = psi
             for inner, link in (("f64", 18), ("f64", 12), ("f32", 12), ("f16s", 12)):

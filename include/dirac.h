@@ -145,6 +145,16 @@ int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x
  *                 float64 CG from the current iterate.
  *   check_every : iterations launched between host convergence checks
  *                 (<= 0: automatic).
+ *   single_launch : run the CG iterations in a single launch, one workgroup
+ *                 per right-hand side with the scalars in registers and no
+ *                 host polling (cg_solve only; small lattices, where the
+ *                 five dependent launches of an iteration are all latency):
+ *                 0 automatic (lattices of at most 1024 sites), 1 always,
+ *                 -1 never.  Same recurrence and stopping rules; results
+ *                 agree with the multi-kernel iteration up to rounding order.
+ *                 A launch runs a bounded number of iterations, and the host
+ *                 launches again until every right-hand side is done.
+ *   reserved    : must be 0.
  */
 typedef struct cg_params {
   double tol;
@@ -153,6 +163,8 @@ typedef struct cg_params {
   double inner_delta;
   int32_t inner_kmax;
   int32_t check_every;
+  int32_t single_launch;
+  int32_t reserved;
 } cg_params;
 
 /* Per right-hand-side results (host). */

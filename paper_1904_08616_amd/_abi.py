@@ -37,7 +37,8 @@ class DiracLaunch(C.Structure):
 
 class CgParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("inner_prec", C.c_int32),
-                ("inner_delta", C.c_double), ("inner_kmax", C.c_int32), ("check_every", C.c_int32)]
+                ("inner_delta", C.c_double), ("inner_kmax", C.c_int32), ("check_every", C.c_int32),
+                ("single_launch", C.c_int32), ("reserved", C.c_int32)]
 
 
 class CgStats(C.Structure):

@@ -61,6 +61,11 @@ DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out
 int run_hop(int prec, int link, int dag, int epi, DslashArgs a, hipStream_t st);
 int hop_partials(const Geom& g);
 
+// CG iterations of every right-hand side of op in one launch (cg_small.hip):
+// at most `chunk` iterations each, from and back to the CgState scalars.
+int cg_small_iterations(const OpInfo& o, const void* U, FieldRef x, FieldRef p, FieldRef r, FieldRef t,
+                        CgState* state, int chunk, hipStream_t st);
+
 // Library-owned device scratch for reductions of API calls (grown on
 // demand, one per device).
 struct Scratch {

@@ -180,11 +180,12 @@ class Operator:
 # -------------------------------------------------------------------- CG ----
 
 def cg(op_hi, U_hi, eta_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec="f64", U_lo=None,
-       inner_delta=0.0, inner_kmax=0, check_every=0, workspace=None, allow_failure=False):
-    """Solve D^dag D x = eta with cg_solve.  Returns (x_int, [stats dict per RHS])."""
+       inner_delta=0.0, inner_kmax=0, check_every=0, workspace=None, allow_failure=False, single_launch=0):
+    """Solve D^dag D x = eta with cg_solve.  Returns (x_int, [stats dict per RHS]).
+    single_launch: 0 automatic, 1 / -1 force the single-launch iteration on / off."""
     lib = abi.load()
     prm = abi.CgParams(float(tol), int(max_iter), _prec(inner_prec), float(inner_delta), int(inner_kmax),
-                       int(check_every))
+                       int(check_every), int(single_launch), 0)
     if x_int is None:
         x_int = torch.zeros_like(eta_int)
     need = int(abi.check(lib.cg_workspace_bytes(C.byref(op_hi.op), C.byref(prm))))

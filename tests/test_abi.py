@@ -111,7 +111,9 @@ def test_cg_argument_checks():
     p = C.c_void_p(1 << 20)
     for params, code in ((abi.CgParams(-1.0, 100, abi.F64, 0.0, 0, 0), abi.EINVAL),
                          (abi.CgParams(1e-10, 0, abi.F64, 0.0, 0, 0), abi.EINVAL),
-                         (abi.CgParams(1e-10, 10, abi.F32, 0.0, 0, 0), abi.EINVAL)):  # U_lo missing
+                         (abi.CgParams(1e-10, 10, abi.F32, 0.0, 0, 0), abi.EINVAL),  # U_lo missing
+                         (abi.CgParams(1e-10, 10, abi.F64, 0.0, 0, 0, 2, 0), abi.EINVAL),
+                         (abi.CgParams(1e-10, 10, abi.F64, 0.0, 0, 0, 0, 1), abi.EINVAL)):
         rc = lib.cg_solve(C.byref(op), p, None, C.c_void_p(2 << 20), C.c_void_p(3 << 20),
                           C.c_void_p(4 << 20), need, C.byref(params), st, None)
         assert rc == code, lib.dirac_last_error()

@@ -56,12 +56,14 @@ def test_c1_4x4x4x4_vs_dense():
     assert abs(st[0]["true_rel_res"] - true_res(U, eta, x, m)) < 1e-12
 
 
+@pytest.mark.parametrize("single", [-1, 1])
 @pytest.mark.parametrize("k", [1, 5, 20])
-def test_iteration_locked(k):
+def test_iteration_locked(k, single):
+    # both iteration paths: the multi-kernel one and the single launch
     dims = (4, 2, 6, 2)
     U, eta = inputs(dims, "haar", seed=1)
     m = 0.1
-    x, st = solve(U, eta, m, tol=1e-30, max_iter=k, allow_failure=True)
+    x, st = solve(U, eta, m, tol=1e-30, max_iter=k, allow_failure=True, single_launch=single)
     assert st[0]["status"] == abi.ENOCONV and st[0]["iters"] == k
     xref, _ = solvers.cg(solvers.ddagd_operator(U, m), eta, fixed_iters=k)
     err = rel_2(x, xref)
@@ -182,6 +184,23 @@ def test_batched_cg_with_stream_kernels(inner):
     for k in range(4):
         assert stb[k]["status"] == abi.OK
         assert true_res(U, src[k], xb[k], m) < 1e-10
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 8, 8, 8)])
+def test_single_launch_matches_multi_kernel(dims, inner):
+    # 8^4 runs 64 iterations per launch: the solve crosses launch boundaries
+    U, eta = inputs(dims, "exp", seed=14, nrhs=2)
+    m = 0.05
+    link = 12
+    xs, ss = solve(U, eta, m, link=link, inner=inner, nrhs=2, single_launch=1)
+    xm, sm = solve(U, eta, m, link=link, inner=inner, nrhs=2, single_launch=-1)
+    for k in range(2):
+        assert ss[k]["status"] == abi.OK and sm[k]["status"] == abi.OK, (ss, sm)
+        assert true_res(U, eta[k], xs[k], m) < 1e-10
+        assert rel_2(xs[k], xm[k]) <= freefield.condition_number(m) * 2e-10
+        # rounding order differs between the paths: inner cycles may end an iteration apart
+        assert abs(ss[k]["iters"] - sm[k]["iters"]) <= max(5, sm[k]["iters"] // 10), (ss[k], sm[k])
 
 
 def test_failure_paths_and_resume():
