@@ -239,6 +239,8 @@ int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params);
  * CG tolerance on the normal equations (first 0.25 tol) is tightened and the
  * solve resumed from the current x (at most 6 passes, max_iter CG
  * iterations in all).
+ * inner_delta <= 0 picks 1e-3 (F32), 0.02 (F16S) or 0.1 (BF16S): the Schur
+ * system lets an F16S inner solve reach a smaller residual than D^dagger D.
  * Arguments as for cg_solve, with b in place of eta; x: the even plane holds
  * the initial guess on entry, x the full solution on exit.  stats: iters
  * and outer summed over the passes, dslash_hi / dslash_lo count applications

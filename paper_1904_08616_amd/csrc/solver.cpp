@@ -327,7 +327,12 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
   FieldRef X = field_of(c.hi, x), R = c.f(c.L.r, DIRAC_F64);
   FieldRef R0 = c.f(c.L.r0, DIRAC_F32), PSI = c.f(c.L.psi, DIRAC_F32), PLO = c.f(c.L.plo, lp),
            TLO = c.f(c.L.tlo, lp);
-  const double delta = prm.inner_delta > 0 ? prm.inner_delta : (lp == DIRAC_F32 ? 1e-3 : 0.1);
+  // Default inner target: 1e-3 for float32 and 0.1 for the 16-bit formats;
+  // the better-conditioned even-odd system lets F16S reach 0.02, which saves
+  // outer cycles (measured flat from 0.05 down to 0.005 on 32^3 x 64; BF16S
+  // falls back to float64 below 0.1 there, as both formats do with D^dag D).
+  const double delta = prm.inner_delta > 0 ? prm.inner_delta
+                       : (lp == DIRAC_F32 ? 1e-3 : (c.eo && lp == DIRAC_F16S ? 0.02 : 0.1));
   const int kmax = prm.inner_kmax > 0 ? prm.inner_kmax : 10000;
 
   std::vector<double> s(n), s_prev(n, 0.0), s_best(n), rho_k(n, 0.0);
