@@ -98,7 +98,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"libdirac.so not found at {LIB_PATH}: build it first "
-            "(python -m paper_1904_08616_amd.build, or __graft_entry__.build()). "
+            "(python -m paper_1904_08616_amd.build). "
             "There is no fallback implementation.")
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
