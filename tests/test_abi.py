@@ -127,6 +127,32 @@ def test_cg_argument_checks():
     assert rc == abi.EINVAL
 
 
+def test_evenodd_argument_checks():
+    # rejected before any device work: no GPU needed
+    lib = abi.load()
+    op = _op(link=abi.LINK12)
+    a, b = C.c_void_p(1 << 20), C.c_void_p(2 << 20)
+    z = C.c_void_p(0)
+    assert lib.dirac_schur_apply(C.byref(op), a, z, b, 0, None) == abi.EINVAL
+    assert lib.dirac_schur_apply(C.byref(op), a, b, b, 0, None) == abi.EINVAL  # in == out
+    assert lib.dirac_schur_apply(C.byref(_op(dims=(3, 4, 4, 4))), a, b, C.c_void_p(3 << 20), 0,
+                                 None) == abi.EINVAL
+    prm = abi.CgParams(1e-10, 100, abi.F64, 0.0, 0, 0)
+    need = lib.cg_workspace_bytes_eo(C.byref(op), C.byref(prm))
+    # one more float64 field than the solve of D^dag D (the reduced source)
+    assert need > lib.cg_workspace_bytes(C.byref(op), C.byref(prm))
+    assert lib.cg_workspace_bytes_eo(C.byref(op), C.byref(abi.CgParams(1e-10, 100, 7, 0.0, 0, 0))) == abi.EINVAL
+    st = (abi.CgStats * 1)()
+    U, bb, x, w = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.c_void_p(4 << 20)
+    for params, work, code in ((abi.CgParams(0.0, 100, abi.F64, 0.0, 0, 0), need, abi.EINVAL),
+                               (abi.CgParams(1e-10, 100, abi.F16S, 0.0, 0, 0), need, abi.EINVAL),  # no U_lo
+                               (prm, need - 256, abi.EWORKSPACE)):
+        rc = lib.cg_solve_eo(C.byref(op), U, None, bb, x, w, work, C.byref(params), st, None)
+        assert rc == code, lib.dirac_last_error()
+    rc = lib.cg_solve_eo(C.byref(op), U, None, bb, bb, w, need, C.byref(prm), st, None)  # b aliases x
+    assert rc == abi.EINVAL
+
+
 def test_launch_config_validation():
     lib = abi.load()
     op = _op()

@@ -249,3 +249,27 @@ def test_cg_with_stream_kernels(inner, remap):
     x, st = solve(U, eta, m, link=12, inner=inner)
     assert st[0]["status"] == abi.OK
     assert true_res(U, eta, x, m) < 1e-10
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_free_field_point_source_propagators(inner):
+    # all 12 point sources at once (one per spin x colour at the origin) on the
+    # free field: batched CG on D^dag D and the even-odd solve of D x = b,
+    # each column against the FFT closed form
+    dims = (8, 4, 6, 8)
+    U = synth.links_unit(dims)
+    src = synth.point_sources(dims)
+    m = 0.2
+    xb, st = solve(U, src, m, link=12, inner=inner, nrhs=12)
+    op = D.Operator(dims, m, "f64", 12, 12)
+    Ui = op.pack_gauge(cuda(U))
+    Ul = None if inner == "f64" else op.like(prec=inner).pack_gauge(cuda(U))
+    xe, se = D.cg_eo(op, Ui, op.pack_spinor(cuda(src)), tol=1e-10, inner_prec=inner, U_lo=Ul)
+    xe = host(op.unpack_spinor(xe))
+    kappa = freefield.condition_number(m)
+    for k in range(12):
+        assert st[k]["status"] == abi.OK and se[k]["status"] == abi.OK
+        ref = freefield.solve_ddagd(src[k], m)
+        assert rel_2(xb[k], ref) <= kappa * 2e-10, k
+        ref_d = freefield.solve_ddagd(wilson.dslash_dagger(U, src[k], m), m)
+        assert rel_2(xe[k], ref_d) <= np.sqrt(kappa) * 2e-10, k
