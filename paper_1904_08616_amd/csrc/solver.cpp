@@ -226,20 +226,43 @@ int run_iterations(Ctx& c, const OpInfo& o, const void* U, FieldRef x, FieldRef 
       if (all) return DIRAC_OK;
     }
   }
+  // Iterations are enqueued in batches between host checks.  An iteration
+  // enqueued after its right-hand side is done still launches its kernels
+  // (gated off, but every block starts), so each batch after the first is
+  // sized from the convergence rate seen so far: the iterations the slowest
+  // active right-hand side still needs to reach its stop2, plus one, at most
+  // check_every.  An underestimate costs one more host check.
+  const int n = c.hi.nrhs;
+  std::vector<double> rho_prev(n, -1.0);
+  int batch = check_every;
   while (true) {
-    for (int k = 0; k < check_every; ++k) {
+    for (int k = 0; k < batch; ++k) {
       int rc = dslash_norm(c, o, U, p.ptr, t.ptr, kGateNotDone, kFinAlpha);
       if (rc != DIRAC_OK) return rc;
       rc = dslash_sub(c, o, U, t.ptr, r.ptr, r.ptr, r.prec, 1, kGateActive, kFinRho);
       if (rc != DIRAC_OK) return rc;
-      rc = hip_status(cg_xp_update(c.vg, c.hi.nrhs, x, p, r, c.dstate, c.st), "cg update");
+      rc = hip_status(cg_xp_update(c.vg, n, x, p, r, c.dstate, c.st), "cg update");
       if (rc != DIRAC_OK) return rc;
     }
     int rc = c.pull();
     if (rc != DIRAC_OK) return rc;
     bool all = true;
-    for (int k = 0; k < c.hi.nrhs; ++k) all &= c.hstate[k].done != 0;
+    double need = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const CgState& S = c.hstate[k];
+      if (S.done) continue;
+      all = false;
+      double est = check_every;  // no usable rate yet
+      if (rho_prev[k] > 0.0 && S.rho > 0.0 && S.rho < rho_prev[k] && S.stop2 > 0.0) {
+        const double rate = std::log(S.rho / rho_prev[k]) / batch;  // log decrease per iteration
+        est = S.rho <= S.stop2 ? 1.0 : std::log(S.stop2 / S.rho) / rate;
+      }
+      est = std::min(est, (double)(S.kmax - S.iters));
+      need = std::max(need, est);
+      rho_prev[k] = S.rho;
+    }
     if (all) return DIRAC_OK;
+    batch = (int)std::min<double>(check_every, std::max(1.0, std::ceil(need) + 1.0));
   }
 }
 
