@@ -182,7 +182,10 @@ def test_pack_roundtrips():
 
 
 def test_full_size_16x16x16x32_f64():
-    # configuration: 16^3 x 32, exp(i 0.3 H) links, m = 0.05, 18- and 12-real
+    # configuration: 16^3 x 32, exp(i 0.3 H) links, m = 0.05, 18- and 12-real;
+    # the default launch and every launch the benchmark may time the headline
+    # with (its cold candidates), each element against the oracle
+    import bench
     dims = (16, 16, 16, 32)
     U, psi = inputs(dims, "exp", seed=0)
     m = 0.05
@@ -190,25 +193,42 @@ def test_full_size_16x16x16x32_f64():
     for link in (18, 12):
         got = _run(U, psi, m, "f64", link, False)
         assert rel_inf(got, ref) <= 1e-13
+    op = D.Operator(dims, m, "f64", 18)
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    for cand in bench.HEADLINE_CANDIDATES:
+        op.set_launch_config(**cand)
+        got = host(op.unpack_spinor(op.apply(Ui, pi)))
+        assert rel_inf(got, ref) <= 1e-13, cand
 
 
 def test_full_size_32x32x32x64_sampled():
     # configuration: 32^3 x 64, exp(i 0.3 H) links, m = 0.02; float64 on a
     # sample of sites (and every corner), float32 / float16s likewise.
+    # Each precision in its default launch and in the autotuner's pick (the
+    # launch the benchmark times).
     dims = (32, 32, 32, 64)
     U, psi = inputs(dims, "exp", seed=0)
     m = 0.02
     sites = sample_sites(dims, 2000)
     ref = wilson.dslash_at(U, psi, m, sites)
+    ref16 = wilson.dslash_at(lowprec.store_links(U, "f16s"), lowprec.store(psi, "f16s"), m, sites)
     Uc, pc = cuda(U), cuda(psi)
-    for prec, link, tol in (("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6)):
+    for prec, link, tol in (("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6), ("f16s", 12, 1.5e-3)):
         op = D.Operator(dims, m, prec, link)
-        out = host(op.unpack_spinor(op.apply(op.pack_gauge(Uc), op.pack_spinor(pc))))
-        got = out[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
-        err = rel_inf(got, ref)
-        print(f"32^3x64 {prec}/{link}: sampled err {err:.2e}")
-        assert err <= tol
-        del out
+        Ui, pi = op.pack_gauge(Uc), op.pack_spinor(pc)
+        for tuned in (False, True):
+            if tuned:
+                op.autotune(Ui, pi, op.empty_spinor())
+            out = host(op.unpack_spinor(op.apply(Ui, pi)))
+            got = out[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
+            err = rel_inf(got, ref16 if prec == "f16s" else ref)
+            print(f"32^3x64 {prec}/{link} {'tuned ' + str(op.launch_config()) if tuned else 'default'}: "
+                  f"sampled err {err:.2e}")
+            assert err <= tol
+            del out
+        del Ui, pi
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
@@ -296,3 +316,31 @@ def test_scaled_formats_tiny_site_maxima(prec, eps):
     assert np.all(np.abs((got - v).real) <= bound) and np.all(np.abs((got - v).imag) <= bound)
     ref = lowprec.store(v, prec)
     assert np.all(np.abs((got - ref).real) <= 2 * bound) and np.all(np.abs((got - ref).imag) <= 2 * bound)
+
+
+def test_full_size_12_point_sources_sampled():
+    # 12 sources on 24^3 x 48 in float32 with 12-real links (the multi-source
+    # workload's shape), default and autotuned launch, on sampled sites
+    # against the oracle on the float32-rounded inputs
+    dims = (24, 24, 24, 48)
+    g = synth.rng(0)
+    U = synth.links_exp(dims, 0.3, g)
+    # a Gaussian part on top of each point source, so that sampled sites away
+    # from the origin are not all zero
+    src = synth.point_sources(dims) + 0.1 * synth.spinor_gauss(dims, g, nrhs=12)
+    m = 0.05
+    sites = sample_sites(dims, 500)
+    U32 = lowprec.store_links(U, "f32")
+    op = D.Operator(dims, m, "f32", 12, 12)
+    Ui, pi = op.pack_gauge(cuda(U)), op.pack_spinor(cuda(src))
+    refs = [wilson.dslash_at(U32, lowprec.store(src[k], "f32"), m, sites) for k in range(12)]
+    for tuned in (False, True):
+        if tuned:
+            op.autotune(Ui, pi, op.empty_spinor())
+        out = host(op.unpack_spinor(op.apply(Ui, pi)))
+        for k in range(12):
+            got = out[k][sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
+            assert rel_inf(got, refs[k]) <= 5e-6, (tuned, k)
+        del out
+    del Ui, pi
+    torch.cuda.empty_cache()
