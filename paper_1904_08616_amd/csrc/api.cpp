@@ -519,6 +519,8 @@ int dirac_force(const dirac_op* op, const void* g_int, const void* psi_int, void
                     "force");
 }
 
+}  // extern "C"
+
 // Launch form of a set of lattices: the one timed fastest when a plan was
 // made for the same set, else t-streaming with t_chunk 4 when every lattice
 // has a streaming tile, else the per-site form.
@@ -568,6 +570,8 @@ int multi_check(int32_t n, const dirac_op* ops, const void* const* U, const void
   return DIRAC_OK;
 }
 }  // namespace
+
+extern "C" {
 
 int dirac_multi_apply(int32_t n, const dirac_op* ops, const void* const* U, const void* const* psi,
                       void* const* chi, int32_t dagger, void* stream) {
