@@ -249,6 +249,17 @@ int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params);
 int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* b, void* x, void* work,
                 int64_t work_bytes, const cg_params* params, cg_stats* stats, void* stream);
 
+/* --------------------------------------------------------- measurement ---- */
+
+/* Memory-bandwidth reference kernels for measurements (not used by any
+ * solve): kind 0 copies `bytes` from src to dst, kind 1 reads src (dst is a
+ * 16-byte sink that is never written in practice), kind 2 writes dst (src is
+ * ignored).  16-byte vectors with non-temporal accesses, four 256-thread
+ * blocks per CU.  bytes: a positive multiple of 16; device buffers, 16-byte
+ * aligned, not overlapping for a copy (DIRAC_EINVAL otherwise).
+ * Asynchronous. */
+int dirac_bandwidth_probe(int32_t kind, const void* src, void* dst, int64_t bytes, void* stream);
+
 /* ------------------------------------------------------------ gradient ---- */
 
 /* Link gradient of a real loss L through chi = D(U) psi (the backward of

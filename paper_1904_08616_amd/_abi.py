@@ -73,6 +73,7 @@ SIGNATURES = {
     "cg_workspace_bytes_eo": (C.c_int64, [_OP, C.POINTER(CgParams)]),
     "cg_solve_eo": (C.c_int, [_OP, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(CgParams),
                               C.POINTER(CgStats), _P]),
+    "dirac_bandwidth_probe": (C.c_int, [C.c_int32, _P, _P, C.c_int64, _P]),
     "dirac_force": (C.c_int, [_OP, _P, _P, _P, C.c_double, C.c_int32, _P]),
     "dirac_multi_apply": (C.c_int, [C.c_int32, _OP, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                                     C.c_int32, _P]),

@@ -219,6 +219,12 @@ def cg_eo(op_hi, U_hi, b_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec
 
 # -------------------------------------------------------- batched lattices ----
 
+def bandwidth_probe(kind, src, dst, nbytes):
+    """Bandwidth reference kernel (dirac_bandwidth_probe): 'copy', 'read' or 'write'."""
+    k = {"copy": 0, "read": 1, "write": 2}[kind]
+    abi.check(abi.load().dirac_bandwidth_probe(k, _ptr(src), _ptr(dst), C.c_int64(nbytes), _stream()))
+
+
 def _ptr_array(ts):
     return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 

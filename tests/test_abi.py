@@ -153,6 +153,18 @@ def test_evenodd_argument_checks():
     assert rc == abi.EINVAL
 
 
+def test_bandwidth_probe_argument_checks():
+    lib = abi.load()
+    a, b = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+    assert lib.dirac_bandwidth_probe(3, a, b, 1024, None) == abi.EINVAL       # kind
+    assert lib.dirac_bandwidth_probe(0, a, b, 1000, None) == abi.EINVAL       # not a multiple of 16
+    assert lib.dirac_bandwidth_probe(0, a, b, 0, None) == abi.EINVAL
+    assert lib.dirac_bandwidth_probe(0, None, b, 1024, None) == abi.EINVAL    # copy without a source
+    assert lib.dirac_bandwidth_probe(1, a, None, 1024, None) == abi.EINVAL    # read without a sink
+    assert lib.dirac_bandwidth_probe(0, a, C.c_void_p((1 << 20) + 8), 1024, None) == abi.EINVAL  # alignment
+    assert lib.dirac_bandwidth_probe(0, a, C.c_void_p((1 << 20) + 512), 1024, None) == abi.EINVAL  # overlap
+
+
 def test_launch_config_validation():
     lib = abi.load()
     op = _op()
