@@ -22,7 +22,8 @@ D x = b is then solved in three steps:
     x_o = (b_o - K_oe x_e) / A.
 
 D^dagger has the same block form with K replaced by the adjoint hop, so its
-Schur complement is D_hat^dagger.
+Schur complement is D_hat^dagger, and D^dagger x = b is solved by the same
+steps with the adjoint hop throughout (CG on D_hat D_hat^dagger).
 
 Fields are canonical full-lattice arrays; an "even field" has zeros on the
 odd sites.  K is taken as D - A, from ``wilson``.
@@ -64,29 +65,30 @@ def schur(U, v, m_q, dagger=False):
     return a * ve - restrict(hop(U, t, m_q, dagger), 0) / a
 
 
-def source(U, b, m_q):
-    """b_hat = b_e - K_eo b_o / A (an even field)."""
+def source(U, b, m_q, dagger=False):
+    """b_hat = b_e - K_eo b_o / A (an even field); K of D^dagger when dagger."""
     a = m_q + 4.0
-    return restrict(b, 0) - restrict(hop(U, restrict(b, 1), m_q), 0) / a
+    return restrict(b, 0) - restrict(hop(U, restrict(b, 1), m_q, dagger), 0) / a
 
 
-def reconstruct(U, b, x_e, m_q):
+def reconstruct(U, b, x_e, m_q, dagger=False):
     """Full solution from its even half: x_o = (b_o - K_oe x_e) / A."""
     a = m_q + 4.0
     xe = restrict(x_e, 0)
-    return xe + (restrict(b, 1) - restrict(hop(U, xe, m_q), 1)) / a
+    return xe + (restrict(b, 1) - restrict(hop(U, xe, m_q, dagger), 1)) / a
 
 
-def solve(U, b, m_q, tol=1e-12, max_iter=100000):
-    """Solve D x = b by the three steps above (CG on the normal equations of
-    D_hat).  Returns (x, info) with info = dict(status, iters,
-    true_rel_res = ||b - D x|| / ||b||)."""
+def solve(U, b, m_q, tol=1e-12, max_iter=100000, dagger=False):
+    """Solve D x = b (D^dagger x = b when dagger) by the three steps above
+    (CG on the normal equations of the Schur complement).  Returns (x, info)
+    with info = dict(status, iters, true_rel_res = ||b - D x|| / ||b||)."""
     b = np.asarray(b, dtype=np.complex128)
-    bh = source(U, b, m_q)
-    eta = schur(U, bh, m_q, dagger=True)
-    op = lambda v: schur(U, schur(U, v, m_q), m_q, dagger=True)  # noqa: E731
+    bh = source(U, b, m_q, dagger)
+    eta = schur(U, bh, m_q, dagger=not dagger)
+    op = lambda v: schur(U, schur(U, v, m_q, dagger), m_q, dagger=not dagger)  # noqa: E731
     xe, info = solvers.cg(op, eta, tol=tol, max_iter=max_iter)
-    x = reconstruct(U, b, xe, m_q)
+    x = reconstruct(U, b, xe, m_q, dagger)
     nb = solvers.norm(b)
-    rel = solvers.norm(b - dslash(U, x, m_q)) / nb if nb > 0 else 0.0
+    dx = dslash_dagger(U, x, m_q) if dagger else dslash(U, x, m_q)
+    rel = solvers.norm(b - dx) / nb if nb > 0 else 0.0
     return x, dict(status=info["status"], iters=info["iters"], true_rel_res=rel)

@@ -79,6 +79,22 @@ def test_solve_matches_dense_solve():
     assert rel2(x, xref) <= np.linalg.cond(M) * 1e-12
 
 
+def test_dagger_solve_matches_dense_solve():
+    dims = (4, 2, 2, 4)
+    g = synth.rng(5)
+    U = synth.links_haar(dims, g)
+    b = synth.spinor_gauss(dims, g)
+    m = 0.1
+    M = wilson.dense_matrix(U, m)
+    xref = wilson.from_vector(np.linalg.solve(M.conj().T, wilson.to_vector(b)), dims)
+    x, info = evenodd.solve(U, b, m, tol=1e-13, dagger=True)
+    assert info["status"] == solvers.OK
+    assert info["true_rel_res"] < 1e-12
+    assert rel2(x, xref) <= np.linalg.cond(M) * 1e-12
+    # and it is not the solution of D x = b
+    assert rel2(x, evenodd.solve(U, b, m, tol=1e-13)[0]) > 1e-3
+
+
 def test_solve_free_field_fft():
     # D^-1 b = (D^dag D)^-1 D^dag b, the latter in closed form for U = 1
     dims = (4, 2, 6, 8)
