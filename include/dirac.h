@@ -227,8 +227,10 @@ int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int,
 /* Bytes of scratch cg_solve_eo needs. */
 int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params);
 
-/* Solve D x = b (eq. (1)) for each of op_hi->nrhs sources through the
- * Schur complement:
+/* Solve D x = b (eq. (1)), or D^dagger x = b when dagger != 0, for each of
+ * op_hi->nrhs sources through the Schur complement (written for D; for
+ * D^dagger every K below is the adjoint hop and the CG runs on
+ * D_hat D_hat^dagger):
  *   b_hat = b_e - K_eo b_o / A,
  *   D_hat^dagger D_hat x_e = D_hat^dagger b_hat   (cg_solve's CG: plain
  *       float64 for inner_prec = DIRAC_F64, Algorithm 1 with an inner solve
@@ -244,10 +246,11 @@ int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params);
  * Arguments as for cg_solve, with b in place of eta; x: the even plane holds
  * the initial guess on entry, x the full solution on exit.  stats: iters
  * and outer summed over the passes, dslash_hi / dslash_lo count applications
- * of D_hat or D_hat^dagger, true_rel_res = ||b - D x|| / ||b||.
+ * of D_hat or D_hat^dagger, true_rel_res = ||b - D x|| / ||b|| (D^dagger in
+ * place of D for the adjoint solve).
  * Synchronises the stream.  (D^dagger D x = eta itself is cg_solve's.) */
 int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* b, void* x, void* work,
-                int64_t work_bytes, const cg_params* params, cg_stats* stats, void* stream);
+                int64_t work_bytes, const cg_params* params, int32_t dagger, cg_stats* stats, void* stream);
 
 /* --------------------------------------------------------- measurement ---- */
 

@@ -71,7 +71,7 @@ SIGNATURES = {
                            C.POINTER(CgStats), _P]),
     "dirac_schur_apply": (C.c_int, [_OP, _P, _P, _P, C.c_int32, _P]),
     "cg_workspace_bytes_eo": (C.c_int64, [_OP, C.POINTER(CgParams)]),
-    "cg_solve_eo": (C.c_int, [_OP, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(CgParams),
+    "cg_solve_eo": (C.c_int, [_OP, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(CgParams), C.c_int32,
                               C.POINTER(CgStats), _P]),
     "dirac_bandwidth_probe": (C.c_int, [C.c_int32, _P, _P, C.c_int64, _P]),
     "dirac_force": (C.c_int, [_OP, _P, _P, _P, C.c_double, C.c_int32, _P]),

@@ -96,6 +96,7 @@ Layout layout(const OpInfo& hi, int inner_prec, bool eo = false) {
 struct Ctx {
   OpInfo hi, lo;
   bool eo = false;  // operator: D_hat of the even-odd form instead of D
+  int eo_dag = 0;   // even-odd form of D^dagger: D_hat^dagger, normal equations D_hat D_hat^dagger
   bool single = false;  // CG iterations in one launch (small lattices)
   Geom vg;          // geometry of the vector operations (even sites only when eo)
   const void* Uhi;
@@ -155,13 +156,15 @@ int hop(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void
 }
 
 // t = D in (store + |t|^2 into `kind`), for precision op o.  Even-odd form:
-// t_e = D_hat in_e, with the odd plane of t holding the intermediate K_oe in_e.
+// t_e = D_hat in_e (D_hat^dagger for the solve with D^dagger), with the odd
+// plane of t holding the intermediate K_oe in_e.
 int dslash_norm(const Ctx& c, const OpInfo& o, const void* U, const void* in, void* t, int gate, int kind) {
   if (c.eo) {
     const double A = o.m_q + 4.0;
-    int rc = hop(c, o, U, in, nullptr, t, 1, 0, 0.0, 1.0, kEpiStore, gate, kFinPlain);
+    const int dag = c.eo_dag;
+    int rc = hop(c, o, U, in, nullptr, t, 1, dag, 0.0, 1.0, kEpiStore, gate, kFinPlain);
     if (rc != DIRAC_OK) return rc;
-    return hop(c, o, U, t, in, t, 0, 0, A, -1.0 / A, kEpiStoreNorm, gate, kind);
+    return hop(c, o, U, t, in, t, 0, dag, A, -1.0 / A, kEpiStoreNorm, gate, kind);
   }
   DslashArgs a = dslash_args(o, U, in, t);
   a.gate = gate;
@@ -170,17 +173,19 @@ int dslash_norm(const Ctx& c, const OpInfo& o, const void* U, const void* in, vo
 }
 
 // dst = src - coef * D^dag in, |dst|^2 into `kind`; dst has precision dprec.
-// Even-odd form: dst_e = src_e - coef * D_hat^dagger in_e, and the odd plane
-// of `in` (a workspace field) receives the intermediate.
+// Even-odd form: dst_e = src_e - coef * D_hat^dagger in_e (D_hat for the solve
+// with D^dagger), and the odd plane of `in` (a workspace field) receives the
+// intermediate.
 int dslash_sub(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void* src, void* dst, int dprec,
                int use_alpha, int gate, int kind) {
   if (c.eo) {
     const int want = (o.prec == DIRAC_F16S || o.prec == DIRAC_BF16S) ? DIRAC_F32 : o.prec;
     if (dprec != want) return set_error(DIRAC_EUNSUPPORTED, "even-odd residual update: format %d", dprec);
     const double A = o.m_q + 4.0;
-    int rc = hop(c, o, U, in, nullptr, (void*)in, 1, 1, 0.0, 1.0, kEpiStore, gate, kFinPlain);
+    const int dag = 1 - c.eo_dag;
+    int rc = hop(c, o, U, in, nullptr, (void*)in, 1, dag, 0.0, 1.0, kEpiStore, gate, kFinPlain);
     if (rc != DIRAC_OK) return rc;
-    return hop(c, o, U, in, in, dst, 0, 1, A, -1.0 / A, kEpiSubNorm, gate, kind, src, use_alpha, dprec);
+    return hop(c, o, U, in, in, dst, 0, dag, A, -1.0 / A, kEpiSubNorm, gate, kind, src, use_alpha, dprec);
   }
   DslashArgs a = dslash_args(o, U, in, dst);
   const FieldRef d = field_as(c.hi, dprec, dst);
@@ -656,13 +661,15 @@ int64_t cg_workspace_bytes_eo(const dirac_op* op_hi, const cg_params* params) {
 }
 
 int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const void* b, void* x, void* work,
-                int64_t work_bytes, const cg_params* params, cg_stats* stats_out, void* stream) {
+                int64_t work_bytes, const cg_params* params, int32_t dagger, cg_stats* stats_out, void* stream) {
   clear_error();
   const auto t0 = std::chrono::steady_clock::now();
   Ctx c;
   cg_params prm;
   int rc = prepare(op_hi, U_hi, U_lo, b, x, work, work_bytes, params, stats_out, true, "cg_solve_eo", c, prm, stream);
   if (rc != DIRAC_OK) return rc;
+  const int dag = dagger ? 1 : 0;  // D^dagger x = b: every hop below adjoint
+  c.eo_dag = dag;
   const int n = c.hi.nrhs;
   const double A = c.hi.m_q + 4.0;
   void* T = c.work + c.L.t;
@@ -689,9 +696,10 @@ int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const
     }
   }
   // b_hat = b_e - K_eo b_o / A (even plane of T), then eta_hat = D_hat^dag b_hat
-  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, b, b, T, 0, 0, 1.0, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
-  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, T, nullptr, T, 1, 1, 0.0, 1.0, kEpiStore, kGateNone, kFinPlain);
-  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, T, T, EH, 0, 1, A, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
+  // (for D^dagger: the adjoint hop, and eta_hat = D_hat b_hat)
+  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, b, b, T, 0, dag, 1.0, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
+  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, T, nullptr, T, 1, 1 - dag, 0.0, 1.0, kEpiStore, kGateNone, kFinPlain);
+  if (rc == DIRAC_OK) rc = hop(c, c.hi, U_hi, T, T, EH, 0, 1 - dag, A, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
   if (rc == DIRAC_OK) rc = eta_norms(c, EH, en);
 
   // The CG stops on the residual of the normal equations; its tolerance
@@ -706,10 +714,10 @@ int cg_solve_eo(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const
     rc = solve_with(c, EH, x, pp, en_pass, stats);
     if (rc != DIRAC_OK) break;
     // x_o = (b_o - K_oe x_e) / A, then r = b - D x on the full lattice
-    rc = hop(c, c.hi, U_hi, x, b, x, 1, 0, 1.0 / A, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
+    rc = hop(c, c.hi, U_hi, x, b, x, 1, dag, 1.0 / A, -1.0 / A, kEpiStore, kGateNone, kFinPlain);
     if (rc != DIRAC_OK) break;
     DslashArgs a = dslash_args(c.hi, U_hi, x, T);
-    rc = run_dslash(DIRAC_F64, DIRAC_F64, c.hi.link, 0, kEpiStore, launch_cfg(c.hi), a, c.st);
+    rc = run_dslash(DIRAC_F64, DIRAC_F64, c.hi.link, dag, kEpiStore, launch_cfg(c.hi), a, c.st);
     if (rc != DIRAC_OK) break;
     const FieldRef TR = field_of(c.hi, T);
     rc = hip_status(axpby(c.hi.g, n, field_of(c.hi, b), TR, nullptr, 1.0, 0.0, -1.0, 0.0, c.st), "residual");

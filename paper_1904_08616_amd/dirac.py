@@ -199,9 +199,10 @@ def cg(op_hi, U_hi, eta_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec=
 
 
 def cg_eo(op_hi, U_hi, b_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec="f64", U_lo=None,
-          inner_delta=0.0, inner_kmax=0, check_every=0, workspace=None, allow_failure=False):
-    """Solve D x = b through the even-odd Schur complement (cg_solve_eo).
-    Returns (x_int, [stats dict per RHS]); true_rel_res is ||b - D x|| / ||b||."""
+          inner_delta=0.0, inner_kmax=0, check_every=0, workspace=None, allow_failure=False, dagger=False):
+    """Solve D x = b (D^dag x = b with dagger) through the even-odd Schur complement
+    (cg_solve_eo).  Returns (x_int, [stats dict per RHS]); true_rel_res is
+    ||b - D x|| / ||b||."""
     lib = abi.load()
     prm = abi.CgParams(float(tol), int(max_iter), _prec(inner_prec), float(inner_delta), int(inner_kmax),
                        int(check_every))
@@ -212,7 +213,7 @@ def cg_eo(op_hi, U_hi, b_int, x_int=None, tol=1e-10, max_iter=100000, inner_prec
         workspace = torch.empty(need, dtype=torch.uint8, device=b_int.device)
     stats = (abi.CgStats * op_hi.nrhs)()
     rc = lib.cg_solve_eo(C.byref(op_hi.op), _ptr(U_hi), _ptr(U_lo), _ptr(b_int), _ptr(x_int), _ptr(workspace),
-                         C.c_int64(workspace.numel()), C.byref(prm), stats, _stream())
+                         C.c_int64(workspace.numel()), C.byref(prm), 1 if dagger else 0, stats, _stream())
     abi.check(rc, allow=(abi.ENOCONV, abi.EBREAKDOWN) if allow_failure else ())
     return x_int, [s.as_dict() for s in stats]
 
@@ -308,6 +309,39 @@ class DiracApply(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             gU = op.force(gi, pi, coeff=1.0)
         return gU, gpsi, None
+
+
+class DSolve(torch.autograd.Function):
+    """x = D^{-1} b (the propagator) by the library's float64 even-odd solve.
+
+    Backward: lambda = D^{-dag} grad_x (the even-odd solve with D^dagger),
+    grad_b = lambda, grad_U = -force(lambda, x).
+    """
+
+    @staticmethod
+    def forward(ctx, U, b, m_q, tol=1e-12, max_iter=100000):
+        lt, lz, ly, lx = U.shape[:4]
+        op = Operator((lx, ly, lz, lt), m_q, "f64", 18, 1)
+        Ui = op.pack_gauge(U.detach())
+        bi = op.pack_spinor(b.detach())
+        x, st = cg_eo(op, Ui, bi, tol=tol, max_iter=max_iter)
+        ctx.op, ctx.tol, ctx.max_iter = op, tol, max_iter
+        ctx.save_for_backward(Ui, x)
+        ctx.stats = st
+        return op.unpack_spinor(x)
+
+    @staticmethod
+    def backward(ctx, gx):
+        op = ctx.op
+        Ui, x = ctx.saved_tensors
+        gi = op.pack_spinor(gx.contiguous())
+        lam, _ = cg_eo(op, Ui, gi, tol=ctx.tol, max_iter=ctx.max_iter, dagger=True)
+        gU = gb = None
+        if ctx.needs_input_grad[1]:
+            gb = op.unpack_spinor(lam)
+        if ctx.needs_input_grad[0]:
+            gU = op.force(lam, x, coeff=-1.0)
+        return gU, gb, None, None, None
 
 
 class DdagDSolve(torch.autograd.Function):

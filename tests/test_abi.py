@@ -147,9 +147,9 @@ def test_evenodd_argument_checks():
     for params, work, code in ((abi.CgParams(0.0, 100, abi.F64, 0.0, 0, 0), need, abi.EINVAL),
                                (abi.CgParams(1e-10, 100, abi.F16S, 0.0, 0, 0), need, abi.EINVAL),  # no U_lo
                                (prm, need - 256, abi.EWORKSPACE)):
-        rc = lib.cg_solve_eo(C.byref(op), U, None, bb, x, w, work, C.byref(params), st, None)
+        rc = lib.cg_solve_eo(C.byref(op), U, None, bb, x, w, work, C.byref(params), 0, st, None)
         assert rc == code, lib.dirac_last_error()
-    rc = lib.cg_solve_eo(C.byref(op), U, None, bb, bb, w, need, C.byref(prm), st, None)  # b aliases x
+    rc = lib.cg_solve_eo(C.byref(op), U, None, bb, bb, w, need, C.byref(prm), 0, st, None)  # b aliases x
     assert rc == abi.EINVAL
 
 

@@ -124,6 +124,42 @@ def test_solve_vs_oracle(inner, link):
     assert err <= (1e-10 + 1e-12) / m * np.linalg.norm(b.ravel()) / np.linalg.norm(xo.ravel())
 
 
+def test_dagger_solve_4x4x4x4_vs_dense():
+    dims = (4, 4, 4, 4)
+    U, b = inputs(dims, "haar", seed=8)
+    m = 0.1
+    x, st = solve_eo(U, b, m, dagger=True)
+    assert st[0]["status"] == abi.OK, st
+    r = np.linalg.norm((b - wilson.dslash_dagger(U, x, m)).ravel()) / np.linalg.norm(b.ravel())
+    assert r < 1e-10
+    assert abs(st[0]["true_rel_res"] - r) < 1e-12
+    M = wilson.dense_matrix(U, m)
+    xref = wilson.from_vector(np.linalg.solve(M.conj().T, wilson.to_vector(b)), dims)
+    assert rel_2(x, xref) <= np.linalg.cond(M) * 2e-10
+    # the adjoint solve is not the solve of D x = b
+    assert rel_2(x, solve_eo(U, b, m)[0]) > 1e-3
+
+
+@pytest.mark.parametrize("inner,link", [("f64", 18), ("f32", 12), ("f16s", 12), ("bf16s", 12)])
+def test_dagger_solve_vs_oracle(inner, link):
+    dims = (8, 8, 8, 16)
+    U, b = inputs(dims, "exp", seed=9)
+    m = 0.02
+    x, st = solve_eo(U, b, m, link=link, inner=inner, dagger=True)
+    assert st[0]["status"] == abi.OK, st
+    r = np.linalg.norm((b - wilson.dslash_dagger(U, x, m)).ravel()) / np.linalg.norm(b.ravel())
+    xo, info = evenodd.solve(U, b, m, tol=1e-12, dagger=True)
+    err = rel_2(x, xo)
+    print(f"eo dagger {inner}/{link} 8^3x16 m=0.02: iters {st[0]['iters']} outer {st[0]['outer']} "
+          f"|b - D^dag x|/|b| {r:.2e} err vs oracle {err:.2e} (oracle iters {info['iters']})")
+    assert r < 1e-10
+    assert abs(st[0]["true_rel_res"] - r) <= 0.05 * r
+    if inner != "f64":
+        assert st[0]["dslash_hi"] <= 4 * st[0]["outer"] + 4, st
+    # |D^-dag| = |D^-1| <= 1/m
+    assert err <= (1e-10 + 1e-12) / m * np.linalg.norm(b.ravel()) / np.linalg.norm(xo.ravel())
+
+
 def test_solve_free_field_closed_form():
     dims = (8, 4, 6, 8)
     U = synth.links_unit(dims)

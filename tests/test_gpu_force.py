@@ -8,7 +8,7 @@ import torch
 
 import synth
 from oracle import force as oforce
-from oracle import solvers, wilson
+from oracle import evenodd, solvers, wilson
 from paper_1904_08616_amd import dirac as D
 from tests.gpu_helpers import cuda, host, inputs, rel_inf
 
@@ -50,6 +50,32 @@ def test_gradcheck_dirac_apply_2x2x2x2():
     pt = cuda(psi).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda u, p: D.DiracApply.apply(u, p, 0.2), (Ut, pt), eps=1e-6,
                                     atol=1e-8, rtol=1e-6)
+
+
+def test_gradcheck_d_solve_2x2x2x2():
+    dims = (2, 2, 2, 2)
+    U, b = inputs(dims, "haar", seed=12)
+    Ut = cuda(U).requires_grad_(True)
+    bt = cuda(b).requires_grad_(True)
+    f = lambda u, p: D.DSolve.apply(u, p, 0.5, 1e-14)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (Ut, bt), eps=1e-6, atol=1e-7, rtol=1e-5)
+
+
+def test_d_solve_gradient_vs_oracle():
+    # L = Re <g, D^-1 b>: dL/db* = lambda = D^-dag g, dL/dU = -link_gradient(U, lambda, x)
+    dims = (4, 2, 6, 4)
+    U, b = inputs(dims, "exp", seed=13)
+    g = synth.spinor_gauss(dims, synth.rng(14))
+    m = 0.2
+    Ut = cuda(U).requires_grad_(True)
+    bt = cuda(b).requires_grad_(True)
+    x = D.DSolve.apply(Ut, bt, m, 1e-13)
+    torch.real(torch.sum(torch.conj(cuda(g)) * x)).backward()
+    xo, _ = evenodd.solve(U, b, m, tol=1e-13)
+    lam, _ = evenodd.solve(U, g, m, tol=1e-13, dagger=True)
+    assert rel_inf(host(x.detach()), xo) <= 1e-10
+    assert rel_inf(host(bt.grad), lam) <= 1e-10
+    assert rel_inf(host(Ut.grad), -oforce.link_gradient(U, lam, xo)) <= 1e-10
 
 
 def test_gradcheck_ddagd_solve_2x2x2x2():
