@@ -492,6 +492,26 @@ def copy_ceiling(torch, D, gib=1.0, reps=5):
     return out
 
 
+def copy_at_size(torch, D, moved, copies, reps=200):
+    """The library's copy kernel moving about ``moved`` bytes per launch (half
+    read, half written), rotated over ``copies`` buffer pairs as the Dslash
+    inputs are: the plain-copy rate at the headline launch's byte count, where
+    a launch of a few tens of microseconds pays its ramp-up and drain."""
+    n = max(16, (moved // 2) // 16 * 16)
+    bufs = [(torch.ones(n, dtype=torch.uint8, device="cuda"), torch.empty(n, dtype=torch.uint8, device="cuda"))
+            for _ in range(copies)]
+    for src, dst in bufs:
+        D.bandwidth_probe("copy", src, dst, n)
+    with Timer(torch) as t:
+        for k in range(reps):
+            src, dst = bufs[k % copies]
+            D.bandwidth_probe("copy", src, dst, n)
+    ms = t.ms / reps
+    del bufs
+    return {"bytes_per_launch": 2 * n, "copies_rotated": copies, "ms": round(ms, 5),
+            "GB/s": round(2 * n / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(dims, U, psi, m_q, budget_s=12.0):
     """The oracle's D on the same lattice, timed on the host with one BLAS thread."""
     from oracle import wilson
@@ -636,6 +656,9 @@ def main(argv=None):
     if copy:
         extra["copy_ceiling"] = copy
         line["roofline"]["frac_of_copy"] = round(gbs / copy["GB/s"], 4)
+        same = copy_at_size(torch, D, bytes_per, copies)
+        extra["copy_at_headline_bytes"] = same
+        line["roofline"]["frac_of_copy_at_headline_bytes"] = round(gbs / same["GB/s"], 4)
     if not a.quick:
         try:
             ms12, _, cfg12 = time_dslash(torch, D, dims, "f64", 12, U, psi, a.steps, a.warmup, m_q=m_q)
@@ -663,6 +686,17 @@ def main(argv=None):
                     "ms": round(msb, 4), "GB/s": round(bb / (msb * 1e-3) / 1e9, 1),
                     "frac": round(bb / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "GFLOP/s": round(FLOPS_PER_SITE * Vb / (msb * 1e-3) / 1e9, 1), "launch": cfgb}
+            # one GPU's share of 32^3x64 split in t over eight GPUs (periodic here,
+            # so the t faces come from the same lattice instead of a neighbour)
+            share = (32, 32, 32, 8)
+            log("Dslash 32^3x8 f64/18 (a share of 32^3x64 over eight GPUs)")
+            Us, ps = gen_inputs(share, seed=0)
+            mss, _, cfgs = time_dslash(torch, D, share, "f64", 18, Us, ps, a.steps, a.warmup, m_q=0.02)
+            bs = site_bytes("f64", 18) * int(np.prod(share))
+            extra["dslash_32x32x32x8_f64_link18"] = {
+                "ms": round(mss, 5), "GB/s": round(bs / (mss * 1e-3) / 1e9, 1),
+                "frac": round(bs / (mss * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launch": cfgs}
+            del Us, ps
             log("CG 32^3x64 m=0.02: float64 vs mixed")
             for inner, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
                 extra[f"cg_32x32x32x64_m0.02_{inner}_link{link}"] = cg_time(torch, D, big, Ub, pb, 0.02, inner,

@@ -202,6 +202,22 @@ def test_full_size_16x16x16x32_f64():
         assert rel_inf(got, ref) <= 1e-13, cand
 
 
+def test_full_size_32x32x32x8_f64():
+    # one GPU's share of 32^3 x 64 split in t over eight (periodic here):
+    # float64 18-real, default launch and the autotuner's pick, every element
+    dims = (32, 32, 32, 8)
+    U, psi = inputs(dims, "exp", seed=0)
+    m = 0.02
+    ref = wilson.dslash(U, psi, m)
+    op = D.Operator(dims, m, "f64", 18)
+    Ui, pi = op.pack_gauge(cuda(U)), op.pack_spinor(cuda(psi))
+    for tuned in (False, True):
+        if tuned:
+            op.autotune(Ui, pi, op.empty_spinor())
+        got = host(op.unpack_spinor(op.apply(Ui, pi)))
+        assert rel_inf(got, ref) <= 1e-13, op.launch_config()
+
+
 def test_full_size_32x32x32x64_sampled():
     # configuration: 32^3 x 64, exp(i 0.3 H) links, m = 0.02; float64 on a
     # sample of sites (and every corner), float32 / float16s likewise.
