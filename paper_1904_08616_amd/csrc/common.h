@@ -141,6 +141,27 @@ template <class R> __device__ __forceinline__ void su3_row2(M3<R>& u) {
   u.e[2][2] = cr(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
 }
 
+// su3_row2 for rows held as decoded 16-bit values: each component is one
+// chain of four fused multiply-adds from `zero` (= 0, kept opaque to the
+// compiler), so that every product reads its 16-bit operands directly
+// (mixed-precision FMA) instead of converting them first.
+template <class R> __device__ __forceinline__ void su3_row2_fma(M3<R>& u, R zero) {
+  auto cr = [zero](Cx<R> a, Cx<R> b, Cx<R> c, Cx<R> d) {  // conj(a*b - c*d)
+    R re = fma(a.re, b.re, zero);
+    re = fma(-a.im, b.im, re);
+    re = fma(-c.re, d.re, re);
+    re = fma(c.im, d.im, re);
+    R im = fma(a.re, b.im, zero);
+    im = fma(a.im, b.re, im);
+    im = fma(-c.re, d.im, im);
+    im = fma(-c.im, d.re, im);
+    return Cx<R>{re, -im};
+  };
+  u.e[2][0] = cr(u.e[0][1], u.e[1][2], u.e[0][2], u.e[1][1]);
+  u.e[2][1] = cr(u.e[0][2], u.e[1][0], u.e[0][0], u.e[1][2]);
+  u.e[2][2] = cr(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
+}
+
 // ------------------------------------------------------- storage formats --
 // Spinor fields: per right-hand side, [parity][NV][Vh] 16-byte vectors,
 // followed for scaled formats by a float scale per site [parity][Vh].
@@ -339,6 +360,19 @@ template <bool BF> struct SpinScaled {
         v[4 * k + j] = {s * dec((unsigned short)(w[j] & 0xFFFFu)), s * dec((unsigned short)(w[j] >> 16))};
     }
   }
+  // The 24 stored values unscaled, and the site scale: load() is s * v.
+  __device__ static __forceinline__ void load_raw(Rsrc f, int Vh, int p, int i, Cx<R> (&v)[12], float& s) {
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 3u * (uint32_t)Vh * 16u);
+    s = bld<float>(f, (uint32_t)i * 4u + scale_off(Vh, p), 0u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 t = bld<uint4>(f, o, (uint32_t)k * (uint32_t)Vh * 16u);
+      unsigned w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[4 * k + j] = {dec((unsigned short)(w[j] & 0xFFFFu)), dec((unsigned short)(w[j] >> 16))};
+    }
+  }
   // Site maximum |v|.
   __device__ static __forceinline__ float site_max(const Cx<R> (&v)[12]) {
     float m = 0.f;
@@ -468,7 +502,9 @@ template <bool BF> struct LinkHalf12 {
       u.e[(2 * k) / 3][(2 * k) % 3] = {dec(t.x & 0xFFFFu), dec(t.x >> 16)};
       u.e[(2 * k + 1) / 3][(2 * k + 1) % 3] = {dec(t.y & 0xFFFFu), dec(t.y >> 16)};
     }
-    su3_row2(u);
+    float zero = 0.f;
+    asm("" : "+v"(zero));
+    su3_row2_fma(u, zero);
   }
 };
 template <> struct LinkFmt<DIRAC_F16S, 12> : LinkHalf12<false> {};
@@ -524,6 +560,23 @@ __device__ __forceinline__ void project(const Cx<R> (&v)[12], Cx<R> (&h)[2][3]) 
   }
 }
 
+// project() for the stored values of a 16-bit site (decoded, unscaled): the
+// same sums, each written as fma(e, +-one, u) with one = 1 kept opaque to the
+// compiler, so that it is a single mixed-precision fused multiply-add reading
+// both 16-bit operands directly instead of two conversions and an addition.
+// The product by +-1 is exact, so every h equals project()'s rounded sum.
+template <int MU, int SG, class R>
+__device__ __forceinline__ void project_fma1(const Cx<R> (&v)[12], Cx<R> (&h)[2][3], R one) {
+  const R sg = SG > 0 ? one : -one;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const Cx<R> d0 = v[6 + a], d1 = v[9 + a];
+    const Cx<R> e0 = sig_d<MU, 0>(d0, d1), e1 = sig_d<MU, 1>(d0, d1);
+    h[0][a] = {fma(e0.re, sg, v[a].re), fma(e0.im, sg, v[a].im)};
+    h[1][a] = {fma(e1.re, sg, v[3 + a].re), fma(e1.im, sg, v[3 + a].im)};
+  }
+}
+
 // acc += (w, SG * s_mu^dag w) for a half spinor w (the hop's contribution).
 template <int MU, int SG, class R>
 __device__ __forceinline__ void reconstruct_add(Cx<R> (&acc)[12], const Cx<R> (&w)[2][3]) {
@@ -541,6 +594,57 @@ __device__ __forceinline__ void reconstruct_add(Cx<R> (&acc)[12], const Cx<R> (&
       acc[9 + a] = acc[9 + a] - l1;
     }
   }
+}
+
+// acc += s (w, SG * s_mu^dag w): the same with the half spinor scaled by s on
+// the way.  The projection, the colour product and s_mu^dag are linear, so a
+// neighbour stored as s * v (a scaled 16-bit site) can be projected and
+// multiplied unscaled and take its scale here, in fused multiply-adds that
+// replace the additions, instead of in 24 multiplications at the load.
+template <int MU, int SG, class R>
+__device__ __forceinline__ void reconstruct_fma(Cx<R> (&acc)[12], const Cx<R> (&w)[2][3], R s) {
+  const R sl = SG > 0 ? s : -s;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[a].re = fma(s, w[0][a].re, acc[a].re);
+    acc[a].im = fma(s, w[0][a].im, acc[a].im);
+    acc[3 + a].re = fma(s, w[1][a].re, acc[3 + a].re);
+    acc[3 + a].im = fma(s, w[1][a].im, acc[3 + a].im);
+    const Cx<R> l0 = sigdag_h<MU, 0>(w[0][a], w[1][a]);
+    const Cx<R> l1 = sigdag_h<MU, 1>(w[0][a], w[1][a]);
+    acc[6 + a].re = fma(sl, l0.re, acc[6 + a].re);
+    acc[6 + a].im = fma(sl, l0.im, acc[6 + a].im);
+    acc[9 + a].re = fma(sl, l1.re, acc[9 + a].re);
+    acc[9 + a].im = fma(sl, l1.im, acc[9 + a].im);
+  }
+}
+
+// su3_mul / su3_dag_mul with every product a fused multiply-add from `zero`
+// (= 0, kept opaque), for links held as decoded 16-bit values: see
+// su3_row2_fma.
+template <class R>
+__device__ __forceinline__ void su3_mul_fma(const M3<R>& u, const Cx<R> (&h)[2][3], Cx<R> (&w)[2][3], R zero) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> t = cmadd(Cx<R>{zero, zero}, u.e[a][0], h[s][0]);
+      t = cmadd(t, u.e[a][1], h[s][1]);
+      t = cmadd(t, u.e[a][2], h[s][2]);
+      w[s][a] = t;
+    }
+}
+template <class R>
+__device__ __forceinline__ void su3_dag_mul_fma(const M3<R>& u, const Cx<R> (&h)[2][3], Cx<R> (&w)[2][3], R zero) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> t = cjmadd(Cx<R>{zero, zero}, u.e[0][a], h[s][0]);
+      t = cjmadd(t, u.e[1][a], h[s][1]);
+      t = cjmadd(t, u.e[2][a], h[s][2]);
+      w[s][a] = t;
+    }
 }
 
 // w = U h, and w = U^dag h, per spin row of the half spinor.

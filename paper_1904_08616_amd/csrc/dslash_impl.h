@@ -95,11 +95,21 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& a, Rsrc Ur, const Rsrc
     for (int r = 0; r < R; ++r) {
       if (!on[r]) continue;
       Cx<Rl> v[12];
-      SI::load(in[r], Vh, q, j, v);
       Cx<Rl> h[2][3], w[2][3];
-      project<MU, -S>(v, h);
-      su3_mul(u, h, w);
-      reconstruct_add<MU, -S>(acc[r], w);
+      if constexpr (SI::kScaled) {
+        float sc;
+        SI::load_raw(in[r], Vh, q, j, v, sc);
+        float one = 1.f, zero = 0.f;
+        asm("" : "+v"(one), "+v"(zero));
+        project_fma1<MU, -S>(v, h, one);
+        su3_mul_fma(u, h, w, zero);
+        reconstruct_fma<MU, -S>(acc[r], w, sc);
+      } else {
+        SI::load(in[r], Vh, q, j, v);
+        project<MU, -S>(v, h);
+        su3_mul(u, h, w);
+        reconstruct_add<MU, -S>(acc[r], w);
+      }
     }
   }
   pin_acc<Rl, R>(acc);
@@ -111,11 +121,21 @@ __device__ __forceinline__ void hop_dir(const DslashArgs& a, Rsrc Ur, const Rsrc
     for (int r = 0; r < R; ++r) {
       if (!on[r]) continue;
       Cx<Rl> v[12];
-      SI::load(in[r], Vh, q, j, v);
       Cx<Rl> h[2][3], w[2][3];
-      project<MU, S>(v, h);
-      su3_dag_mul(u, h, w);
-      reconstruct_add<MU, S>(acc[r], w);
+      if constexpr (SI::kScaled) {
+        float sc;
+        SI::load_raw(in[r], Vh, q, j, v, sc);
+        float one = 1.f, zero = 0.f;
+        asm("" : "+v"(one), "+v"(zero));
+        project_fma1<MU, S>(v, h, one);
+        su3_dag_mul_fma(u, h, w, zero);
+        reconstruct_fma<MU, S>(acc[r], w, sc);
+      } else {
+        SI::load(in[r], Vh, q, j, v);
+        project<MU, S>(v, h);
+        su3_dag_mul(u, h, w);
+        reconstruct_add<MU, S>(acc[r], w);
+      }
     }
   }
   pin_acc<Rl, R>(acc);

@@ -50,17 +50,28 @@ __device__ __forceinline__ void pin12(Cx<R> (&acc)[12]) {
 
 // One hop of eq. (1) from an already loaded neighbour spinor v:
 // FWD: acc += U (1 - S gamma_mu) v;  backward: acc += U^dag (1 + S gamma_mu) v.
-template <int MU, bool DAG, bool FWD, class R>
+// MIX (links held as decoded 16-bit values): the colour products as chains
+// of fused multiply-adds from an opaque zero, which read the 16-bit link
+// entries directly.
+template <int MU, bool DAG, bool FWD, bool MIX = false, class R>
 __device__ __forceinline__ void hop_apply(const M3<R>& u, const Cx<R> (&v)[12], Cx<R> (&acc)[12]) {
   constexpr int S = DAG ? -1 : 1;
   Cx<R> h[2][3], w[2][3];
+  R zero = R(0);
+  if constexpr (MIX) asm("" : "+v"(zero));
   if constexpr (FWD) {
     project<MU, -S>(v, h);
-    su3_mul(u, h, w);
+    if constexpr (MIX)
+      su3_mul_fma(u, h, w, zero);
+    else
+      su3_mul(u, h, w);
     reconstruct_add<MU, -S>(acc, w);
   } else {
     project<MU, S>(v, h);
-    su3_dag_mul(u, h, w);
+    if constexpr (MIX)
+      su3_dag_mul_fma(u, h, w, zero);
+    else
+      su3_dag_mul(u, h, w);
     reconstruct_add<MU, S>(acc, w);
   }
 }
@@ -185,14 +196,14 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       // x: both neighbours are in the tile (it spans all of x)
       LF::load(Ur, Vh, p, 0, i, u);
       cur_s.get(col_xp, v);
-      hop_apply<0, DAG, true>(u, v, acc);
+      hop_apply<0, DAG, true, SI::kScaled>(u, v, acc);
       {
         int pb, ib;
         at(ccol_xm, cpar ^ 1, t, pb, ib);
         LF::load(Ur, Vh, pb, 0, ib, u);
       }
       cur_s.get(col_xm, v);
-      hop_apply<0, DAG, false>(u, v, acc);
+      hop_apply<0, DAG, false, SI::kScaled>(u, v, acc);
       nxt_s.put(tid, nxt);  // psi(tn) waits in LDS for the t hop and the next step
       pin12(acc);
       // y
@@ -204,7 +215,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         at(ccol_yp, cpar ^ 1, t, pf, jf);
         SI::load(in, Vh, pf, jf, v);
       }
-      hop_apply<1, DAG, true>(u, v, acc);
+      hop_apply<1, DAG, true, SI::kScaled>(u, v, acc);
       {
         int pb, ib;
         at(ccol_ym, cpar ^ 1, t, pb, ib);
@@ -214,7 +225,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         else
           SI::load(in, Vh, pb, ib, v);
       }
-      hop_apply<1, DAG, false>(u, v, acc);
+      hop_apply<1, DAG, false, SI::kScaled>(u, v, acc);
       pin12(acc);
       // z
       LF::load(Ur, Vh, p, 2, i, u);
@@ -225,7 +236,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         at(ccol_zp, cpar ^ 1, t, pf, jf);
         SI::load(in, Vh, pf, jf, v);
       }
-      hop_apply<2, DAG, true>(u, v, acc);
+      hop_apply<2, DAG, true, SI::kScaled>(u, v, acc);
       {
         int pb, ib;
         at(ccol_zm, cpar ^ 1, t, pb, ib);
@@ -235,7 +246,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         else
           SI::load(in, Vh, pb, ib, v);
       }
-      hop_apply<2, DAG, false>(u, v, acc);
+      hop_apply<2, DAG, false, SI::kScaled>(u, v, acc);
       pin12(acc);
       // t: the hop from psi(tn) now, and the hop from psi(t) carried to tn
       if constexpr (DOWN)
@@ -243,7 +254,7 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       else
         LF::load(Ur, Vh, p, 3, i, u);  // U_t(n)
       nxt_s.get(tid, v);
-      hop_apply<3, DAG, !DOWN>(u, v, acc);
+      hop_apply<3, DAG, !DOWN, SI::kScaled>(u, v, acc);
       cur_s.get(tid, v);
       Cx<Rl> h[2][3];
       project<3, SC>(v, h);
