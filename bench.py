@@ -530,6 +530,7 @@ def cpu_baseline(dims, U, psi, m_q, budget_s=12.0):
             if time.perf_counter() - t0 > budget_s:
                 break
         el = time.perf_counter() - t0
+        cg = oracle_small_cg()
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
@@ -539,7 +540,37 @@ def cpu_baseline(dims, U, psi, m_q, budget_s=12.0):
             "sample": f"{n} full float64 applications of D on {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
                       f"({el:.1f} s, NumPy, one thread)",
             "ms_per_step": round(1e3 * el / n, 2),
-            "host_cpus": os.cpu_count()}
+            "gflops": round(FLOPS_PER_SITE * V * n / el / 1e9, 3),
+            "cg_4x4x4x4_m0.1": cg,
+            "host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_small_cg():
+    """The oracle's CG on D^dag D to 1e-10 on 4^4 (Haar links, seed 0,
+    m_q = 0.1; the inputs of the single-launch GPU timing), run to
+    completion on one host thread."""
+    import synth
+    from oracle import solvers, wilson
+    dims = (4, 4, 4, 4)
+    g = synth.rng(0)
+    U = synth.links_haar(dims, g)
+    eta = synth.spinor_gauss(dims, g)
+    t0 = time.perf_counter()
+    _, info = solvers.cg(solvers.ddagd_operator(U, 0.1), eta, tol=1e-10)
+    el = time.perf_counter() - t0
+    return {"ms": round(1e3 * el, 1), "iters": info["iters"], "status": info["status"]}
 
 
 def main(argv=None):
