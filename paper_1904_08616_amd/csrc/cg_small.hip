@@ -120,11 +120,8 @@ __global__ void __launch_bounds__(kSmallBlock) k_cg_small(SmallCgArgs a) {
       const int p = n >= Vh ? 1 : 0, i = n - p * Vh;
       Cx<Ro> o[12];
       site_op<P, LK, false>(da, Ur, pr, p, i, o);
-      SO::store(tr, Vh, p, i, o);
-      Cx<Ro> q[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) q[k] = o[k];
-      SO::round(q);
+      Cx<Ro> q[12];  // the value as stored
+      SO::store_q(tr, Vh, p, i, o, q);
 #pragma unroll
       for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
     }

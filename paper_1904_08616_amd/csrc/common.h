@@ -254,6 +254,14 @@ template <> struct SpinFmt<DIRAC_F64> {
     }
   }
   __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
+  // store(), returning in q the value left in memory (v itself here).
+  template <int AUX = 0>
+  __device__ static __forceinline__ void store_q(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
+                                                 Cx<R> (&q)[12]) {
+    store<AUX>(f, Vh, p, i, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) q[c] = v[c];
+  }
   template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
     const uint32_t o = (uint32_t)i * 16u + plane_off(p, 12u * (uint32_t)Vh * 16u);
@@ -301,6 +309,14 @@ template <> struct SpinFmt<DIRAC_F32> {
     }
   }
   __device__ static __forceinline__ void round(Cx<R> (&)[12]) {}
+  // store(), returning in q the value left in memory (v itself here).
+  template <int AUX = 0>
+  __device__ static __forceinline__ void store_q(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
+                                                 Cx<R> (&q)[12]) {
+    store<AUX>(f, Vh, p, i, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) q[c] = v[c];
+  }
   template <int AUX = 0>
   __device__ static __forceinline__ void store(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12]) {
     const uint32_t o = (uint32_t)i * 16u + plane_off(p, 6u * (uint32_t)Vh * 16u);
@@ -415,6 +431,29 @@ template <bool BF> struct SpinScaled {
         const float re = (v[4 * k + j].re * pre) * inv;
         const float im = (v[4 * k + j].im * pre) * inv;
         w[j] = (unsigned)enc(re) | ((unsigned)enc(im) << 16);
+      }
+      bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));
+    }
+    bst<AUX>(f, (uint32_t)i * 4u + scale_off(Vh, p), 0u, m);
+  }
+  // store(), returning in q the value left in memory (round() of v), both
+  // from the one encoding: q = m * decode(payload).
+  template <int AUX = 0>
+  __device__ static __forceinline__ void store_q(Rsrc f, int Vh, int p, int i, const Cx<R> (&v)[12],
+                                                 Cx<R> (&q)[12]) {
+    const float m = site_max(v);
+    float pre, inv;
+    site_factors(m, pre, inv);
+    const uint32_t o = (uint32_t)i * 16u + plane_off(p, 3u * (uint32_t)Vh * 16u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      unsigned w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned short re = enc((v[4 * k + j].re * pre) * inv);
+        const unsigned short im = enc((v[4 * k + j].im * pre) * inv);
+        w[j] = (unsigned)re | ((unsigned)im << 16);
+        q[4 * k + j] = {m * dec(re), m * dec(im)};
       }
       bst<AUX>(f, o, (uint32_t)k * (uint32_t)Vh * 16u, make_uint4(w[0], w[1], w[2], w[3]));
     }

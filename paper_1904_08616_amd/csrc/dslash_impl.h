@@ -184,19 +184,16 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int p, int i, i
     convert12(acc[r], o);
     if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
       const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
+      Cx<Ro> q[12];  // the value as stored
       if (a.nt_store)
-        SO::template store<2>(orsrc, Vh, p, i, o);
+        SO::template store_q<2>(orsrc, Vh, p, i, o, q);
       else
-        SO::template store<0>(orsrc, Vh, p, i, o);
+        SO::template store_q<0>(orsrc, Vh, p, i, o, q);
       if constexpr (EPI == kEpiStoreNorm) {
         // <p, D^dag t_stored> = Re <D p, t_stored>: pair the exact result with
         // the value as stored, so that the CG step matches the vector the
         // next kernel actually applies D^dag to (they differ for scaled
         // 16-bit formats).
-        Cx<Ro> q[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) q[k] = o[k];
-        SO::round(q);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;

@@ -278,15 +278,12 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
     const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
     if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+      Cx<Ro> q[12];  // the value as stored
       if (a.nt_store)
-        SO::template store<2>(orsrc, Vh, p, i, o);
+        SO::template store_q<2>(orsrc, Vh, p, i, o, q);
       else
-        SO::template store<0>(orsrc, Vh, p, i, o);
+        SO::template store_q<0>(orsrc, Vh, p, i, o, q);
       if constexpr (EPI == kEpiStoreNorm) {
-        Cx<Ro> q[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) q[k] = o[k];
-        SO::round(q);
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) sum += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;

@@ -72,14 +72,11 @@ k_hop(DslashArgs a) {
     }
     if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
       const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
-      SO::store(orsrc, Vh, p, i, o);
+      Cx<Ro> q[12];  // the value as stored
+      SO::store_q(orsrc, Vh, p, i, o, q);
       if constexpr (EPI == kEpiStoreNorm) {
         // the exact result paired with the value as stored, as in the full
         // stencil (the two differ for the scaled 16-bit formats)
-        Cx<Ro> q[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) q[k] = o[k];
-        SO::round(q);
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
