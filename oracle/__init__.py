@@ -19,6 +19,9 @@ against the paper rather than to be fast:
                    precision "Residual Guided CG" of Algorithm 1;
 * ``force``     -- the gradient of a real loss with respect to the links
                    (projected spinor outer products);
+* ``lowprec``   -- the storage formats of the low-precision inner solve
+                   (binary32, and binary16 / bfloat16 with a per-site scale),
+                   as roundings of float64 values;
 * ``evenodd``   -- the even-odd (Schur complement) form of D x = b: the
                    even-site operator D_hat = A - K_eo K_oe / A, the reduced
                    source, the odd-site reconstruction and the solve.
