@@ -290,7 +290,7 @@ STREAM_CASES = [
 
 @pytest.mark.parametrize("dims,tile,tc", STREAM_CASES)
 @pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
-                                           ("f16s", 12, 1.5e-3)])
+                                           ("f16s", 12, 1.5e-3), ("bf16s", 12, 1.2e-2)])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
     U, psi = inputs(dims, "exp", seed=10)

@@ -189,6 +189,23 @@ def test_batched_sources_match_single(inner):
         assert rel_2(xb[k], xs) <= 2e-10 / m
 
 
+@pytest.mark.parametrize("inner", ["f64", "f16s"])
+def test_batched_dagger_sources_match_single(inner):
+    dims = (8, 4, 4, 8)
+    g = synth.rng(17)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)[:3] + 0.1 * synth.spinor_gauss(dims, g, nrhs=3)
+    src[1] *= 1e-3
+    m = 0.05
+    xb, stb = solve_eo(U, src, m, link=12, inner=inner, nrhs=3, dagger=True)
+    for k in range(3):
+        assert stb[k]["status"] == abi.OK, stb
+        r = np.linalg.norm((src[k] - wilson.dslash_dagger(U, xb[k], m)).ravel()) / np.linalg.norm(src[k].ravel())
+        assert r < 1e-10
+        xs, _ = solve_eo(U, src[k], m, link=12, inner=inner, dagger=True)
+        assert rel_2(xb[k], xs) <= 2e-10 / m
+
+
 def test_fewer_iterations_than_cg_on_normal_equations():
     dims = (8, 8, 8, 16)
     U, b = inputs(dims, "exp", seed=8)
