@@ -312,20 +312,26 @@ class DiracApply(torch.autograd.Function):
 
 
 class DSolve(torch.autograd.Function):
-    """x = D^{-1} b (the propagator) by the library's float64 even-odd solve.
+    """x = D^{-1} b (the propagator) by the library's even-odd solve, to a
+    float64 residual ||b - D x|| / ||b|| < tol; inner_prec "f32", "f16s" or
+    "bf16s" runs its CG as Algorithm 1 with that inner format (the tolerance
+    is still met in float64).
 
-    Backward: lambda = D^{-dag} grad_x (the even-odd solve with D^dagger),
-    grad_b = lambda, grad_U = -force(lambda, x).
+    Backward: lambda = D^{-dag} grad_x (the even-odd solve with D^dagger, same
+    inner format), grad_b = lambda, grad_U = -force(lambda, x).
     """
 
     @staticmethod
-    def forward(ctx, U, b, m_q, tol=1e-12, max_iter=100000):
+    def forward(ctx, U, b, m_q, tol=1e-12, max_iter=100000, inner_prec="f64"):
         lt, lz, ly, lx = U.shape[:4]
         op = Operator((lx, ly, lz, lt), m_q, "f64", 18, 1)
         Ui = op.pack_gauge(U.detach())
+        Ul = None
+        if inner_prec != "f64":
+            Ul = op.like(prec=inner_prec, link=18 if inner_prec == "f32" else 12).pack_gauge(U.detach())
         bi = op.pack_spinor(b.detach())
-        x, st = cg_eo(op, Ui, bi, tol=tol, max_iter=max_iter)
-        ctx.op, ctx.tol, ctx.max_iter = op, tol, max_iter
+        x, st = cg_eo(op, Ui, bi, tol=tol, max_iter=max_iter, inner_prec=inner_prec, U_lo=Ul)
+        ctx.op, ctx.tol, ctx.max_iter, ctx.inner, ctx.Ul = op, tol, max_iter, inner_prec, Ul
         ctx.save_for_backward(Ui, x)
         ctx.stats = st
         return op.unpack_spinor(x)
@@ -335,13 +341,14 @@ class DSolve(torch.autograd.Function):
         op = ctx.op
         Ui, x = ctx.saved_tensors
         gi = op.pack_spinor(gx.contiguous())
-        lam, _ = cg_eo(op, Ui, gi, tol=ctx.tol, max_iter=ctx.max_iter, dagger=True)
+        lam, _ = cg_eo(op, Ui, gi, tol=ctx.tol, max_iter=ctx.max_iter, inner_prec=ctx.inner, U_lo=ctx.Ul,
+                       dagger=True)
         gU = gb = None
         if ctx.needs_input_grad[1]:
             gb = op.unpack_spinor(lam)
         if ctx.needs_input_grad[0]:
             gU = op.force(lam, x, coeff=-1.0)
-        return gU, gb, None, None, None
+        return gU, gb, None, None, None, None
 
 
 class DdagDSolve(torch.autograd.Function):

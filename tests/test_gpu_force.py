@@ -61,15 +61,17 @@ def test_gradcheck_d_solve_2x2x2x2():
     assert torch.autograd.gradcheck(f, (Ut, bt), eps=1e-6, atol=1e-7, rtol=1e-5)
 
 
-def test_d_solve_gradient_vs_oracle():
-    # L = Re <g, D^-1 b>: dL/db* = lambda = D^-dag g, dL/dU = -link_gradient(U, lambda, x)
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
+def test_d_solve_gradient_vs_oracle(inner):
+    # L = Re <g, D^-1 b>: dL/db* = lambda = D^-dag g, dL/dU = -link_gradient(U, lambda, x);
+    # a mixed inner solve still meets the float64 tolerance, so the same bound holds
     dims = (4, 2, 6, 4)
     U, b = inputs(dims, "exp", seed=13)
     g = synth.spinor_gauss(dims, synth.rng(14))
     m = 0.2
     Ut = cuda(U).requires_grad_(True)
     bt = cuda(b).requires_grad_(True)
-    x = D.DSolve.apply(Ut, bt, m, 1e-13)
+    x = D.DSolve.apply(Ut, bt, m, 1e-13, 100000, inner)
     torch.real(torch.sum(torch.conj(cuda(g)) * x)).backward()
     xo, _ = evenodd.solve(U, b, m, tol=1e-13)
     lam, _ = evenodd.solve(U, g, m, tol=1e-13, dagger=True)
