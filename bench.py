@@ -361,6 +361,26 @@ def bench_multi_rhs(torch, D, steps, warmup):
     return out
 
 
+def profile_multi_rhs(torch, D, launch, steps):
+    """The 12-source Dslash of bench_multi_rhs in a fixed launch, preceded by
+    a 1 GiB device copy (the reference the byte counters are scaled by)."""
+    import synth
+    dims = (24, 24, 24, 48)
+    V = int(np.prod(dims))
+    g = synth.rng(0)
+    U = synth.links_exp(dims, 0.3, g)
+    src = synth.point_sources(dims)
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    del a, b
+    cfg = json.loads(launch)
+    ms, _, used = time_dslash(torch, D, dims, "f32", 12, U, src, steps, 3, nrhs=12, m_q=0.05, launch=cfg)
+    by = site_bytes("f32", 12, 12) * V
+    return {"ms": round(ms, 4), "GB/s": round(by / (ms * 1e-3) / 1e9, 1), "launch": used}
+
+
 def bench_multi_lattice(torch, D, steps):
     """One persistent hipGraph launch over 8^4, 12^4, 16^3 x 32 and 24^3 x 48
     (float32, 12-real links, own seeds and masses) against four separate
@@ -590,6 +610,9 @@ def main(argv=None):
     ap.add_argument("--profile-eo", action="store_true",
                     help="only the even-odd Schur operator and the 32^3x64 solves of D x = b (float64 and F16S "
                          "inner), one JSON line; for kernel traces of the half-lattice hops")
+    ap.add_argument("--profile-mrhs", default=None, metavar="LAUNCH",
+                    help="only the 12-source float32 Dslash on 24^3x48 in this JSON launch configuration (no "
+                         "tuning), after a 1 GiB copy that calibrates the byte counters; for counter runs")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); "
@@ -606,6 +629,10 @@ def main(argv=None):
         Ub, pb = gen_inputs(big, seed=0)
         res = {inner: cg_time(torch, D, big, Ub, pb, 0.02, inner, link=12) for inner in ("f64", "f32", "f16s")}
         print(json.dumps({"cg_32x32x32x64_m0.02_link12": res}), flush=True)
+        return 0
+    if a.profile_mrhs:
+        print(json.dumps({"dslash_24x24x24x48_f32_link12_12rhs": profile_multi_rhs(torch, D, a.profile_mrhs,
+                                                                                    a.steps)}), flush=True)
         return 0
     if a.profile_eo:
         big = (32, 32, 32, 64)
