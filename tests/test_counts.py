@@ -52,3 +52,10 @@ def test_bench_compulsory_bytes():
     assert bench.site_bytes("f32", 12, nrhs=12) == 2496
     no_reuse = g["input_bytes_per_stencil_fp64"] + 24 * 8
     assert no_reuse == 3072  # the paper's inputs plus the written output
+
+
+def test_bench_refuses_several_gpus(capsys):
+    # one GPU only: asking for more exits with status 2 and says why, before
+    # anything touches a device
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU only" in capsys.readouterr().err
