@@ -144,13 +144,15 @@ def test_evenodd_argument_checks():
     assert lib.cg_workspace_bytes_eo(C.byref(op), C.byref(abi.CgParams(1e-10, 100, 7, 0.0, 0, 0))) == abi.EINVAL
     st = (abi.CgStats * 1)()
     U, bb, x, w = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.c_void_p(4 << 20)
-    for params, work, code in ((abi.CgParams(0.0, 100, abi.F64, 0.0, 0, 0), need, abi.EINVAL),
-                               (abi.CgParams(1e-10, 100, abi.F16S, 0.0, 0, 0), need, abi.EINVAL),  # no U_lo
-                               (prm, need - 256, abi.EWORKSPACE)):
-        rc = lib.cg_solve_eo(C.byref(op), U, None, bb, x, w, work, C.byref(params), 0, st, None)
-        assert rc == code, lib.dirac_last_error()
-    rc = lib.cg_solve_eo(C.byref(op), U, None, bb, bb, w, need, C.byref(prm), 0, st, None)  # b aliases x
-    assert rc == abi.EINVAL
+    for dagger in (0, 1):  # the adjoint solve is validated the same way
+        assert lib.dirac_schur_apply(C.byref(op), a, b, b, dagger, None) == abi.EINVAL  # in == out
+        for params, work, code in ((abi.CgParams(0.0, 100, abi.F64, 0.0, 0, 0), need, abi.EINVAL),
+                                   (abi.CgParams(1e-10, 100, abi.F16S, 0.0, 0, 0), need, abi.EINVAL),  # no U_lo
+                                   (prm, need - 256, abi.EWORKSPACE)):
+            rc = lib.cg_solve_eo(C.byref(op), U, None, bb, x, w, work, C.byref(params), dagger, st, None)
+            assert rc == code, lib.dirac_last_error()
+        rc = lib.cg_solve_eo(C.byref(op), U, None, bb, bb, w, need, C.byref(prm), dagger, st, None)  # b aliases x
+        assert rc == abi.EINVAL
 
 
 def test_bandwidth_probe_argument_checks():
