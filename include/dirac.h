@@ -140,9 +140,12 @@ int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x
  *                 0.1 (F16S/BF16S).
  *   inner_kmax  : cap on one inner solve (<= 0: 10000).  Every cycle after
  *                 the first is further capped at twice the first cycle's
- *                 iteration count (at least 50); two capped cycles in a row,
- *                 or six cycles without progress, finish the solve with
- *                 float64 CG from the current iterate.
+ *                 iteration count (at least 50).  A cycle that does not
+ *                 lower the best true residual so far counts as stalled;
+ *                 from the third stalled cycle on no search direction is
+ *                 carried into the next cycle, and two capped cycles in a
+ *                 row, or six stalled cycles, finish the solve with float64
+ *                 CG from the current iterate (stats.fallback).
  *   check_every : iterations launched between host convergence checks
  *                 (<= 0: automatic).
  *   single_launch : run the CG iterations in a single launch, one workgroup
@@ -174,7 +177,8 @@ typedef struct cg_stats {
   int32_t outer;       /* outer cycles (true-residual recomputations) */
   int32_t dslash_hi;   /* high-precision D or D^dag applications */
   int32_t dslash_lo;   /* low-precision D or D^dag applications */
-  int32_t pad;
+  int32_t fallback;    /* 0, or the number of Algorithm 1 cycles after which
+                          the safeguards handed the solve to float64 CG */
   double true_rel_res; /* final ||eta - A x|| / ||eta||, float64 */
   double seconds;      /* wall time of the whole solve */
 } cg_stats;

@@ -59,8 +59,7 @@ def store(v, fmt):
     raise ValueError(f"unknown format {fmt!r}")
 
 
-def store_links(U, fmt):
-    """Round links to the storage format (links are never scaled: |U_ij| <= 1)."""
+def _round_links(U, fmt):
     U = np.asarray(U, dtype=np.complex128)
     if fmt == "f64":
         return U
@@ -72,3 +71,31 @@ def store_links(U, fmt):
     if fmt == "bf16s":
         return _round_bf16(np.real(U)) + 1j * _round_bf16(np.imag(U))
     raise ValueError(f"unknown format {fmt!r}")
+
+
+def third_row(U):
+    """Row 2 of an SU(3) matrix from its rows 0 and 1.
+
+    For a special unitary matrix the rows form a right-handed orthonormal
+    basis of C^3: each row is the complex conjugate of the cross product of
+    the other two (unitarity gives orthogonality, det = 1 fixes the phase).
+    So row 2 = conj(row 0 x row 1)."""
+    a = U[..., 0, :]
+    b = U[..., 1, :]
+    return np.conj(np.cross(a, b))
+
+
+def store_links(U, fmt, link=18):
+    """Round links to the storage format (links are never scaled: |U_ij| <= 1).
+
+    ``link=12`` emulates the two-row storage: rows 0 and 1 are rounded and
+    row 2 is rebuilt from the rounded rows (``third_row``, evaluated in
+    float64), as the library does in registers."""
+    R = _round_links(U, fmt)
+    if link == 18:
+        return R
+    if link != 12:
+        raise ValueError(f"link must be 18 or 12, got {link!r}")
+    out = R.copy()
+    out[..., 2, :] = third_row(R)
+    return out

@@ -43,11 +43,11 @@ class CgParams(C.Structure):
 
 class CgStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("outer", C.c_int32),
-                ("dslash_hi", C.c_int32), ("dslash_lo", C.c_int32), ("pad", C.c_int32),
+                ("dslash_hi", C.c_int32), ("dslash_lo", C.c_int32), ("fallback", C.c_int32),
                 ("true_rel_res", C.c_double), ("seconds", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _P = C.c_void_p

@@ -507,6 +507,8 @@ int cg_mixed(Ctx& c, const void* eta, void* x, const cg_params& prm, const std::
     }
     if (stagnated) {
       *fallback = true;  // finish in float64
+      for (int k = 0; k < n; ++k)
+        if (!conv[k]) stats[k].fallback = stats[k].outer;
       return DIRAC_OK;
     }
   }

@@ -154,6 +154,81 @@ def test_mixed_first_iterations_vs_oracle_large(inner):
     assert dres <= 1e-3
 
 
+# Bars of the cycle-by-cycle comparison: the GPU and the oracle's format
+# emulation round differently (float32 arithmetic against float64 arithmetic
+# rounded to the format), so iterates drift apart slowly.  Simulated on the
+# CPU (the oracle with a relative perturbation of 2e-7, resp. 1e-5 for F16S,
+# on every output of its low-precision operator), five cycles on these
+# lattices move the iterate by <= 2.3e-7 (F16S 6.8e-5) and the true residual
+# by <= 6.5e-5 (F16S 1.9e-2); starting each cycle from p0 = r0 instead of the
+# carried direction moves them by >= 2.5e-3 and >= 0.13.
+CYCLE_BARS = {"f32": (1e-5, 1e-3), "f16s": (1e-3, 5e-2)}
+
+
+@pytest.mark.parametrize("inner", ["f32", "f16s"])
+@pytest.mark.parametrize("dims,seed", [((4, 4, 4, 4), 1), ((8, 8, 8, 8), 2)])
+def test_mixed_cycles_vs_oracle(dims, seed, inner):
+    # Algorithm 1 across outer cycles, carried direction included: after
+    # each of the first five cycles (max_iter = the oracle's cumulative
+    # inner count; inner_delta 0.3 keeps the cycles short) the GPU has run
+    # the same cycles as the oracle's emulation of the same formats (12-real
+    # links), and its iterate and true residual agree within CYCLE_BARS.
+    # 4^4 runs the single-launch iterations, 8^4 the multi-kernel ones.
+    U, eta = inputs(dims, "exp", seed=seed)
+    m, delta = 0.05, 0.3
+    xbar, rbar = CYCLE_BARS[inner]
+    _, full = solvers.mixed_cg(U, eta, m, tol=1e-10, inner_fmt=inner, delta=delta, link=12)
+    counts = np.cumsum([c["iters"] for c in full["cycles"]])[:5]
+    for k, n in enumerate(counts, 1):
+        n = int(n)
+        x, st = solve(U, eta, m, link=12, inner=inner, inner_delta=delta, max_iter=n, allow_failure=True)
+        xo, io = solvers.mixed_cg(U, eta, m, tol=1e-10, inner_fmt=inner, delta=delta, max_iter=n, link=12)
+        xr, ir = solvers.mixed_cg(U, eta, m, tol=1e-10, inner_fmt=inner, delta=delta, max_iter=n, link=12,
+                                  carry=False)
+        dx = rel_2(x, xo)
+        dres = abs(st[0]["true_rel_res"] - io["true_rel_res"]) / io["true_rel_res"]
+        r_or = true_res(U, eta, x, m)
+        print(f"{inner} {dims} cycle {k} (N={n}): GPU iters {st[0]['iters']} outer {st[0]['outer']}, "
+              f"|x - x_oracle| {dx:.2e}, residual {st[0]['true_rel_res']:.6e} vs {io['true_rel_res']:.6e} "
+              f"(rel {dres:.1e}); restart variant |x| {rel_2(xr, xo):.1e}")
+        assert st[0]["iters"] == n and st[0]["outer"] == k and io["outer"] == k
+        assert abs(r_or - st[0]["true_rel_res"]) <= 1e-6 * r_or  # the reported residual is the oracle's
+        assert dx <= xbar and dres <= rbar
+        if k > 1:  # the bars tell the carried direction from a restart
+            assert rel_2(xr, xo) > xbar or abs(ir["true_rel_res"] - io["true_rel_res"]) > rbar * io["true_rel_res"]
+
+
+def test_mixed_safeguards_vs_oracle():
+    # bfloat16 links at m = 0.02, inner_delta 0.7: the solve walks the whole
+    # safeguard path (a cycle that raises the residual, the carried
+    # direction dropped from the third stalled cycle, the hand-over to
+    # float64 CG at the sixth).  The GPU must hand over too, converge, and
+    # its cycles up to the first stall must match the oracle's.
+    dims = (4, 4, 4, 4)
+    g = synth.rng(3)
+    om = synth.gauge_transform_haar(dims, g)
+    U = synth.links_pure_gauge(om)
+    eta = synth.spinor_gauss(dims, g)
+    m, delta = 0.02, 0.7
+    xo, io = solvers.mixed_cg(U, eta, m, tol=1e-10, inner_fmt="bf16s", delta=delta, link=12, max_iter=5000)
+    assert io["fallback"] and io["status"] == solvers.OK
+    x, st = solve(U, eta, m, link=12, inner="bf16s", inner_delta=delta, max_iter=5000)
+    print(f"oracle: cycles {[(c['iters'], c['carried']) for c in io['cycles']]}, history "
+          f"{['%.2e' % h for h in io['history']]}; GPU: {st[0]}")
+    assert st[0]["status"] == abi.OK and true_res(U, eta, x, m) < 1e-10
+    assert st[0]["fallback"] > 0
+    # the cycles before the residual first rises, one by one
+    h = io["history"]
+    first_rise = next(k for k in range(1, len(h)) if h[k] >= min(h[:k]))
+    counts = np.cumsum([c["iters"] for c in io["cycles"]])
+    for k in range(1, first_rise):
+        n = int(counts[k - 1])
+        _, sk = solve(U, eta, m, link=12, inner="bf16s", inner_delta=delta, max_iter=n, allow_failure=True)
+        print(f"cycle {k}: GPU residual {sk[0]['true_rel_res']:.4e} oracle {h[k]:.4e}")
+        assert sk[0]["iters"] == n and sk[0]["outer"] == k
+        assert abs(sk[0]["true_rel_res"] - h[k]) <= 0.05 * h[k]
+
+
 @pytest.mark.parametrize("inner", ["f64", "f32"])
 def test_batched_rhs_match_single(inner):
     dims = (8, 4, 4, 8)
@@ -323,7 +398,7 @@ def test_full_size_32x32x32x64_solves_sampled_residual():
     Ui = op.pack_gauge(cuda(U))
     e = op.pack_spinor(cuda(eta))
     bench.tune_for_solve(op, Ui, e)
-    for inner in ("f64", "f16s"):
+    for inner in ("f64", "f32", "f16s"):
         Ul = None
         if inner != "f64":
             lo = op.like(prec=inner, link=12)

@@ -29,6 +29,34 @@ def test_force_kernel_vs_oracle(dims):
     assert rel_inf(host(Ft), -1.5 * ref) <= 1e-13
 
 
+def test_force_kernel_16x16x16x16_vs_oracle():
+    # the differentiation workload's lattice (16^4, exp(i 0.3 H) links,
+    # m = 0.1): the force kernel on the vectors of its gradient, Y = D X and
+    # X = (D^dag D)^{-1} phi as the library computes them, against the
+    # oracle's projected outer products of the same vectors, element by
+    # element; and the solve gradient -[F(DX, lam) + F(D lam, X)] (lam is a
+    # second solve of the same system, so it matches X only to kappa * tol)
+    dims = (16, 16, 16, 16)
+    U, phi = inputs(dims, "exp", seed=0)
+    m = 0.1
+    op = D.Operator(dims, m, "f64", 18)
+    Ui = op.pack_gauge(cuda(U))
+    x, st = D.cg(op, Ui, op.pack_spinor(cuda(phi)), tol=1e-13)
+    y = op.apply(Ui, x)
+    F = host(op.force(y, x, coeff=1.0))
+    X, Y = host(op.unpack_spinor(x)), host(op.unpack_spinor(y))
+    ref = oforce.link_gradient(U, Y, X)
+    err = rel_inf(F, ref)
+    print(f"16^4 force kernel vs oracle: {err:.2e}")
+    assert err <= 1e-13
+    Ut = cuda(U).requires_grad_(True)
+    Xt = D.DdagDSolve.apply(Ut, cuda(phi), m, 1e-13)
+    torch.real(torch.sum(torch.conj(cuda(phi)) * Xt)).backward()
+    gerr = rel_inf(host(Ut.grad), oforce.solve_link_gradient(U, m, X, X))
+    print(f"16^4 solve gradient vs oracle on the library's X: {gerr:.2e}")
+    assert gerr <= 6561 * 2e-13  # kappa of the free field at m = 0.1 times both tolerances
+
+
 def test_dirac_apply_autograd_vs_oracle():
     dims = (4, 2, 6, 2)
     U, psi = inputs(dims, "haar", seed=3)
@@ -164,6 +192,7 @@ def test_c5_16x16x16x16_finite_differences():
         print(f"  fd {f:+.9e}  pred {p_:+.9e}  diff {f - p_:+.2e}")
     print(f"16^4 FD check: median |dS| {scale:.3e}, worst |fd - pred| {dev.max():.2e}, "
           f"worst relative {np.max(dev / np.maximum(np.abs(preds), scale)):.2e}")
-    # rounding of S (~1e5, float64) divided by 2h bounds the attainable
-    # agreement; the directional derivatives are O(scale)
-    assert np.all(dev <= 1e-3 * np.maximum(np.abs(preds), scale))
+    # rounding of S (~1e5, float64: ~1e-11) divided by 2h = 2e-6 bounds the
+    # attainable agreement near 5e-6 absolute, 2e-5 of the median |dS|; the
+    # observed worst relative deviation on the MI355X is 7.0e-5
+    assert np.all(dev <= 2e-4 * np.maximum(np.abs(preds), scale))

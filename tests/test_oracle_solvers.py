@@ -106,16 +106,100 @@ def test_mixed_cg_reaches_true_residual(fmt, delta):
     assert rel2(x, xref) < 1e-5
 
 
-def test_mixed_cg_carried_direction_helps():
-    # The carried search direction (p0 = r0 + beta0 p~) must not cost more
-    # inner iterations than restarting every cycle from p0 = r0.
-    dims = (4, 2, 6, 2)
-    g = synth.rng(6)
+def _exp_case(dims, seed):
+    g = synth.rng(seed)
     U = synth.links_exp(dims, 0.3, g)
+    return U, synth.spinor_gauss(dims, g)
+
+
+# (lattice, seed, m, delta, iteration counts N): each N spans at least three
+# outer cycles of Algorithm 1 with these inner targets.
+IDENTITY_CASES = [
+    ((4, 2, 6, 2), 6, 0.02, 0.3, (40, 60, 80)),
+    ((4, 4, 4, 4), 1, 0.05, 0.3, (25, 40, 60)),
+    ((4, 2, 6, 2), 6, 0.02, 0.1, (60, 80)),
+]
+
+
+@pytest.mark.parametrize("dims,seed,m,delta,ns", IDENTITY_CASES)
+def test_mixed_cg_exact_inner_reproduces_plain_cg(dims, seed, m, delta, ns):
+    # Algorithm 1, carried search direction (Kernel Description): with an
+    # exact (float64) inner solve the carried p_0 = r0 + beta_0 p~ continues
+    # plain CG's recurrence in the new normalisation, so after N inner
+    # iterations the solution is plain CG's N-th iterate, whatever the cycle
+    # boundaries.  A wrong sign or index in p~, a beta_0 without rho_k or
+    # inverted, a carried pre-update direction or a missing rescale of the
+    # correction all break this by 1e-3 or more.
+    U, eta = _exp_case(dims, seed)
+    op = solvers.ddagd_operator(U, m)
+    for n in ns:
+        x, info = solvers.mixed_cg(U, eta, m, tol=1e-14, inner_fmt="f64", delta=delta, max_iter=n)
+        assert info["iters"] == n and len(info["cycles"]) >= 3, info["cycles"]
+        assert all(c["carried"] for c in info["cycles"][1:])
+        xc, _ = solvers.cg(op, eta, fixed_iters=n)
+        err = rel2(x, xc)
+        print(f"{dims} N={n} cycles {[c['iters'] for c in info['cycles']]}: |x - x_cg| {err:.1e}")
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("dims,seed,m,delta,ns", IDENTITY_CASES)
+def test_mixed_cg_restart_breaks_the_identity(dims, seed, m, delta, ns):
+    # Negative control of the pin above: restarting every cycle from
+    # p_0 = r0 (no carried direction) is a valid solver but not plain CG.
+    U, eta = _exp_case(dims, seed)
+    op = solvers.ddagd_operator(U, m)
+    for n in ns:
+        x, info = solvers.mixed_cg(U, eta, m, tol=1e-14, inner_fmt="f64", delta=delta, max_iter=n,
+                                   carry=False)
+        assert not any(c["carried"] for c in info["cycles"])
+        xc, _ = solvers.cg(op, eta, fixed_iters=n)
+        assert rel2(x, xc) > 1e-4
+
+
+def test_mixed_cg_safeguards_drop_carry_then_fall_back():
+    # bfloat16 links at m = 0.02 with a loose inner target: after a cycle
+    # that raises the true residual, the next ones stay above the best
+    # residual so far.  From the third stalled cycle on no direction is
+    # carried, and the sixth stalled cycle hands the solve to float64 CG,
+    # which still reaches the target.
+    dims = (4, 4, 4, 4)
+    g = synth.rng(3)
+    om = synth.gauge_transform_haar(dims, g)
+    U = synth.links_pure_gauge(om)
     eta = synth.spinor_gauss(dims, g)
-    _, carried = solvers.mixed_cg(U, eta, 0.02, inner_fmt="f32", delta=1e-3)
-    _, plain = solvers.cg(solvers.ddagd_operator(U, 0.02), eta, tol=1e-10)
-    assert carried["iters"] < 1.5 * plain["iters"]
+    x, info = solvers.mixed_cg(U, eta, 0.02, tol=1e-10, inner_fmt="bf16s", delta=0.7, max_iter=5000)
+    assert info["status"] == solvers.OK and info["fallback"]
+    h = info["history"]
+    best = h[0]
+    stall = 0
+    for k, c in enumerate(info["cycles"]):
+        assert c["carried"] == (k > 0 and stall < 3), (k, stall, info["cycles"])
+        if h[k + 1] < best:
+            best, stall = h[k + 1], 0
+        else:
+            stall += 1
+    assert stall == 6
+    assert info["true_rel_res"] < 1e-10
+    res = np.linalg.norm((eta - wilson.ddagd(U, x, 0.02)).ravel()) / np.linalg.norm(eta.ravel())
+    assert res < 1e-10
+
+
+def test_third_row_rebuilds_su3():
+    # row 2 = conj(row 0 x row 1) for special unitary matrices (both
+    # generators give exact SU(3)); for a U(3) matrix with det != 1 it is off
+    # by the phase conj(det), which pins the role of det = 1.
+    g = synth.rng(11)
+    for U in (synth.links_haar((2, 2, 2, 2), g), synth.links_exp((2, 2, 2, 2), 0.3, g)):
+        assert np.max(np.abs(lowprec.third_row(U) - U[..., 2, :])) < 1e-14
+    V = synth.links_haar((2, 2, 2, 2), g) * np.exp(0.4j)
+    det = np.linalg.det(V)
+    assert np.max(np.abs(lowprec.third_row(V) - np.conj(det)[..., None] * V[..., 2, :])) < 1e-14
+    # 12-real storage keeps rows 0 and 1 as rounded and rebuilds row 2 from them
+    R = lowprec.store_links(U, "f16s", 12)
+    R18 = lowprec.store_links(U, "f16s")
+    assert np.array_equal(R[..., :2, :], R18[..., :2, :])
+    assert np.max(np.abs(R[..., 2, :] - lowprec.third_row(R18))) == 0.0
+    assert 0 < np.max(np.abs(R[..., 2, :] - R18[..., 2, :])) < 3e-3
 
 
 def test_lowprec_formats():
