@@ -14,7 +14,9 @@
  * General rules for every entry point:
  *   - Pointers are DEVICE pointers owned by the caller unless marked "host".
  *     The library keeps no reference to them after the call returns (except
- *     a graph plan, see dirac_multi_plan_create).
+ *     a graph plan, see dirac_multi_plan_create), and it never allocates
+ *     device memory: scratch comes from caller workspaces sized by the
+ *     *_workspace_bytes calls.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Work is enqueued asynchronously on it; only cg_solve, dirac_field_dot,
  *     dirac_autotune and the plan/graph calls synchronise the stream.
@@ -113,11 +115,21 @@ int dirac_dagger_apply(const dirac_op* op, const void* U_int, const void* psi_in
 int dirac_mdagm_apply(const dirac_op* op, const void* U_int, const void* psi_int, void* tmp_int,
                       void* chi_int, void* stream);
 
+/* Bytes of device workspace dirac_field_dot needs for op (reduction
+ * partials and per-right-hand-side scalars); negative status on a bad op. */
+int64_t dirac_field_dot_workspace_bytes(const dirac_op* op);
+
 /* <a, b> = sum conj(a) b over all sites, per right-hand side, accumulated in
- * float64 with a fixed-order (deterministic) reduction.  out_host receives
- * nrhs complex values as (re, im) pairs.  Synchronises the stream. */
-int dirac_field_dot(const dirac_op* op, const void* a_int, const void* b_int, double* out_host,
-                    void* stream);
+ * float64 with a fixed-order (deterministic) reduction: the inner products of
+ * Algorithm 1 (Kernel Description).  a_int, b_int: internal fields of op.
+ * work: caller-owned device workspace of work_bytes >=
+ * dirac_field_dot_workspace_bytes(op), 256-byte aligned, not overlapping the
+ * fields (DIRAC_EWORKSPACE if too small); its contents on entry do not
+ * matter.  out_host (host) receives nrhs complex values as (re, im) pairs.
+ * Synchronises the stream.  Calls that share one workspace must not overlap
+ * in time. */
+int dirac_field_dot(const dirac_op* op, const void* a_int, const void* b_int, void* work, int64_t work_bytes,
+                    double* out_host, void* stream);
 
 /* y = a x + y on internal fields of one precision, complex scalar a given by
  * (a_re, a_im), same for every right-hand side. */

@@ -169,13 +169,61 @@ std::string device_name() {
   return s;
 }
 
+// Cache keys carry a format version: entries written by a library whose
+// kernels or launch parameters differed are not read back.
+constexpr int kCfgVersion = 2;
+
 std::string cfg_key(const OpInfo& o) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s|%dx%dx%dx%d|p%d|l%d|n%d", device_name().c_str(), o.g.X, o.g.Y, o.g.Z,
-           o.g.T, o.prec, o.link, o.nrhs);
+  snprintf(buf, sizeof(buf), "v%d|%s|%dx%dx%dx%d|p%d|l%d|n%d", kCfgVersion, device_name().c_str(), o.g.X, o.g.Y,
+           o.g.Z, o.g.T, o.prec, o.link, o.nrhs);
   return buf;
 }
 
+}  // namespace
+
+// Whether launch configuration c fits geometry g with nrhs right-hand sides
+// (nullptr) or why not; normalises the fields the chosen kernel ignores.
+const char* check_cfg(const Geom& g, int nrhs, LaunchCfg& c) {
+  if (c.lds) {
+    if (c.remap < 0 || c.remap > 7) return "xcd_remap of the streaming kernel is a 3-bit mask";
+    if (!stream_fits(g, c.sy, c.sz, c.tc))
+      return "the streaming tile must divide the lattice and have 32 to 256 columns, t_chunk >= 1";
+    c.S = 64;
+    c.R = 1;
+    c.lds = 1;
+  } else {
+    if (c.S != 64 && c.S != 128 && c.S != 256) return "block_sites must be 64, 128 or 256";
+    const bool split = c.R == -2 || c.R == -4;
+    if (!split && (c.R < 1 || c.R > 4)) return "rhs_per_thread must be 1..4, or -2/-4 (split)";
+    if (split && nrhs != 1) return "the direction-split kernel takes nrhs = 1";
+    c.remap = c.remap ? 1 : 0;
+    c.sy = c.sz = c.tc = 1;
+  }
+  c.nt = c.nt ? 1 : 0;
+  return nullptr;
+}
+
+namespace {
+
+// Geometry and nrhs of a cache key (see cfg_key); false if it does not parse.
+bool parse_key(const char* key, Geom* g, int* nrhs) {
+  int v = 0, L[4], p = 0, l = 0, n = 0;
+  const char* q = std::strchr(key, '|');
+  if (std::sscanf(key, "v%d|", &v) != 1 || v != kCfgVersion || q == nullptr) return false;
+  q = std::strchr(q + 1, '|');  // past the device name
+  if (q == nullptr || std::sscanf(q, "|%dx%dx%dx%d|p%d|l%d|n%d", &L[0], &L[1], &L[2], &L[3], &p, &l, &n) != 7)
+    return false;
+  for (int d = 0; d < 4; ++d)
+    if (L[d] < 2 || (L[d] & 1)) return false;
+  if (n < 1 || n > kMaxRhs) return false;
+  *g = make_geom(L);
+  *nrhs = n;
+  return true;
+}
+
+// Every line is checked like dirac_set_launch_config's argument; lines of
+// another format version, or that do not fit their geometry, are skipped.
 void load_cache_file_locked() {
   if (g_cfg_loaded) return;
   g_cfg_loaded = true;
@@ -187,6 +235,9 @@ void load_cache_file_locked() {
   LaunchCfg c;
   while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds, &c.nt, &c.sy, &c.sz,
                      &c.tc) == 9) {
+    Geom g;
+    int nrhs = 0;
+    if (!parse_key(key, &g, &nrhs) || check_cfg(g, nrhs, c) != nullptr) continue;
     c.tuned = 1;
     g_cfg[key] = c;
   }
@@ -246,49 +297,19 @@ static void store_cfg(const OpInfo& o, const LaunchCfg& c, bool to_file) {
   std::fclose(f);
 }
 
-// ---------------------------------------------------------- scratch -----
-namespace {
-struct DevScratch {
-  double* partials = nullptr;
-  int64_t partial_cap = 0;
-  CgState* state = nullptr;
+// Workspace of dirac_field_dot: the per-right-hand-side scalar states, then
+// the reduction partials (two per block and right-hand side).
+struct DotLayout {
+  int64_t state, partials, total;
 };
-std::mutex g_scratch_mu;
-std::map<int, DevScratch> g_scratch;
-}  // namespace
-
-int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return set_error(DIRAC_EDEVICE, "hipGetDevice failed");
-  std::lock_guard<std::mutex> lk(g_scratch_mu);
-  DevScratch& s = g_scratch[dev];
-  if (s.state == nullptr) {
-    if (hipMalloc(&s.state, sizeof(CgState) * kMaxRhs) != hipSuccess)
-      return set_error(DIRAC_EDEVICE, "scratch allocation failed");
-    if (hipMemset(s.state, 0, sizeof(CgState) * kMaxRhs) != hipSuccess)
-      return set_error(DIRAC_EDEVICE, "scratch clear failed");
-  }
-  if (s.partial_cap < partial_doubles) {
-    if (s.partials) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(s.partials);
-      s.partials = nullptr;
-    }
-    int64_t cap = std::max<int64_t>(partial_doubles, 1 << 16);
-    if (hipMalloc(&s.partials, cap * sizeof(double)) != hipSuccess) {
-      s.partial_cap = 0;
-      return set_error(DIRAC_EDEVICE, "scratch allocation failed");
-    }
-    s.partial_cap = cap;
-  }
-  (void)nrhs;
-  out->partials = s.partials;
-  out->state = s.state;
-  return DIRAC_OK;
+static DotLayout dot_layout(const OpInfo& o) {
+  DotLayout L;
+  L.state = 0;
+  L.partials = align256(sizeof(CgState) * kMaxRhs);
+  const int64_t nparts = 2 * ((o.g.Vh + 255) / 256);
+  L.total = L.partials + align256(nparts * o.nrhs * 2 * (int64_t)sizeof(double));
+  return L;
 }
-
-// Serialises API calls that use the library scratch.
-static std::mutex g_api_mu;
 
 }  // namespace dirac
 
@@ -459,22 +480,37 @@ int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int,
   return run_hop(o.prec, o.link, dag, kEpiStore, a, st);
 }
 
-int dirac_field_dot(const dirac_op* op, const void* a, const void* b, double* out_host, void* stream) {
+int64_t dirac_field_dot_workspace_bytes(const dirac_op* op) {
   clear_error();
   OpInfo o;
-  CHECK(check_op(op, &o, "dirac_field_dot"));
-  CHECK(check_ptr(a, "a_int", "dirac_field_dot"));
-  CHECK(check_ptr(b, "b_int", "dirac_field_dot"));
-  if (out_host == nullptr) return set_error(DIRAC_EINVAL, "dirac_field_dot: out_host is NULL");
-  std::lock_guard<std::mutex> lk(g_api_mu);
-  Scratch s;
-  const int64_t nparts = 2 * ((o.g.Vh + 255) / 256);
-  CHECK(lib_scratch(nparts * o.nrhs * 2, o.nrhs, &s));
+  CHECK(check_op(op, &o, "dirac_field_dot_workspace_bytes"));
+  return dot_layout(o).total;
+}
+
+int dirac_field_dot(const dirac_op* op, const void* a, const void* b, void* work, int64_t work_bytes,
+                    double* out_host, void* stream) {
+  clear_error();
+  const char* what = "dirac_field_dot";
+  OpInfo o;
+  CHECK(check_op(op, &o, what));
+  CHECK(check_ptr(a, "a_int", what));
+  CHECK(check_ptr(b, "b_int", what));
+  if (work == nullptr || ((uintptr_t)work & 255u) != 0)
+    return set_error(DIRAC_EINVAL, "%s: work is NULL or not 256-byte aligned", what);
+  if (out_host == nullptr) return set_error(DIRAC_EINVAL, "%s: out_host is NULL", what);
+  const DotLayout L = dot_layout(o);
+  if (work_bytes < L.total)
+    return set_error(DIRAC_EWORKSPACE, "%s: workspace needs %lld bytes, got %lld", what, (long long)L.total,
+                     (long long)work_bytes);
+  const int64_t sb = spinor_buffer_bytes(o);
+  if (overlap(work, L.total, a, sb) || overlap(work, L.total, b, sb))
+    return set_error(DIRAC_EINVAL, "%s: workspace overlaps a field", what);
   hipStream_t st = (hipStream_t)stream;
-  RedTarget red{s.partials, s.state, kFinPlain};
+  CgState* state = (CgState*)((char*)work + L.state);
+  RedTarget red{(double*)((char*)work + L.partials), state, kFinPlain};
   CHECK(hip_status(dot(o.g, o.nrhs, field_of(o, a), field_of(o, b), red, st), "dot"));
-  std::vector<CgState> hs(o.nrhs);
-  CHECK(hip_status(hipMemcpyAsync(hs.data(), s.state, sizeof(CgState) * o.nrhs, hipMemcpyDeviceToHost, st),
+  CgState hs[kMaxRhs];
+  CHECK(hip_status(hipMemcpyAsync(hs, state, sizeof(CgState) * o.nrhs, hipMemcpyDeviceToHost, st),
                    "dot readback"));
   CHECK(hip_status(hipStreamSynchronize(st), "dot sync"));
   for (int r = 0; r < o.nrhs; ++r) {
@@ -785,29 +821,11 @@ int dirac_set_launch_config(const dirac_op* op, const dirac_launch* cfg) {
   OpInfo o;
   CHECK(check_op(op, &o, "dirac_set_launch_config"));
   if (cfg == nullptr) return set_error(DIRAC_EINVAL, "dirac_set_launch_config: cfg is NULL");
-  LaunchCfg c{cfg->block_sites, cfg->rhs_per_thread, cfg->xcd_remap ? 1 : 0, cfg->lds ? 1 : 0,
-              cfg->nt_store ? 1 : 0, cfg->tile_y, cfg->tile_z, cfg->t_chunk, 1};
-  if (c.lds) {
-    if (cfg->xcd_remap < 0 || cfg->xcd_remap > 7)
-      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: xcd_remap of the streaming kernel is a 3-bit mask");
-    c.remap = cfg->xcd_remap;
-    if (!stream_fits(o.g, c.sy, c.sz, c.tc))
-      return set_error(DIRAC_EINVAL,
-                       "dirac_set_launch_config: tile %d x %d x %d (x, y, z) must divide the lattice and have "
-                       "32 to 256 columns, t_chunk >= 1",
-                       o.g.X, c.sy, c.sz);
-    c.S = 64;
-    c.R = 1;
-  } else {
-    if (c.S != 64 && c.S != 128 && c.S != 256)
-      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: block_sites must be 64, 128 or 256");
-    const bool split = c.R == -2 || c.R == -4;
-    if (!split && (c.R < 1 || c.R > 4))
-      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: rhs_per_thread must be 1..4, or -2/-4 (split)");
-    if (split && o.nrhs != 1)
-      return set_error(DIRAC_EINVAL, "dirac_set_launch_config: the direction-split kernel takes nrhs = 1");
-    c.sy = c.sz = c.tc = 1;
-  }
+  LaunchCfg c{cfg->block_sites, cfg->rhs_per_thread, cfg->xcd_remap, cfg->lds ? 1 : 0,
+              cfg->nt_store, cfg->tile_y, cfg->tile_z, cfg->t_chunk, 1};
+  if (const char* why = check_cfg(o.g, o.nrhs, c))
+    return set_error(DIRAC_EINVAL, "dirac_set_launch_config: %s (tile %d x %d x %d, t_chunk %d)", why, o.g.X,
+                     cfg->tile_y, cfg->tile_z, cfg->t_chunk);
   store_cfg(o, c, false);
   return DIRAC_OK;
 }

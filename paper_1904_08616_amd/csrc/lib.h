@@ -66,14 +66,6 @@ int hop_partials(const Geom& g);
 int cg_small_iterations(const OpInfo& o, const void* U, FieldRef x, FieldRef p, FieldRef r, FieldRef t,
                         CgState* state, int chunk, hipStream_t st);
 
-// Library-owned device scratch for reductions of API calls (grown on
-// demand, one per device).
-struct Scratch {
-  double* partials;
-  CgState* state;
-};
-int lib_scratch(int64_t partial_doubles, int nrhs, Scratch* out);
-
 // Multi-lattice persistent launch (multi.hip): per-site form, or t-streaming
 // tiles with a common t_chunk (optionally dealt to XCDs in contiguous runs).
 struct MultiCfg {

@@ -142,9 +142,20 @@ class Operator:
                                              _ptr(out), _stream()))
         return out
 
-    def dot(self, a, b):
+    def dot_workspace(self, device="cuda"):
+        """A device workspace for ``dot`` (kept by the operator and reused)."""
+        need = int(abi.check(self.lib.dirac_field_dot_workspace_bytes(C.byref(self.op))))
+        ws = getattr(self, "_dot_ws", None)
+        if ws is None or ws.numel() < need or ws.device != torch.device(device):
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+            self._dot_ws = ws
+        return ws
+
+    def dot(self, a, b, workspace=None):
         out = (C.c_double * (2 * self.nrhs))()
-        abi.check(self.lib.dirac_field_dot(C.byref(self.op), _ptr(a), _ptr(b), out, _stream()))
+        ws = self.dot_workspace(a.device) if workspace is None else workspace
+        abi.check(self.lib.dirac_field_dot(C.byref(self.op), _ptr(a), _ptr(b), _ptr(ws), C.c_int64(ws.numel()),
+                                           out, _stream()))
         v = np.frombuffer(out, dtype=np.float64).copy()
         return v[0::2] + 1j * v[1::2]
 

@@ -155,6 +155,41 @@ def test_evenodd_argument_checks():
         assert rc == abi.EINVAL
 
 
+def test_field_dot_workspace_and_checks():
+    lib = abi.load()
+    # partials: two float64 per 256-site block, both parities, per right-hand
+    # side; after 12 scalar states of 112 bytes (each part rounded up to 256
+    # bytes)
+    for dims, nrhs in (((4, 4, 4, 4), 1), ((32, 32, 32, 64), 12), ((8, 6, 4, 10), 3)):
+        op = _op(dims=dims, nrhs=nrhs)
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        nparts = 2 * ((V // 2 + 255) // 256)
+        want = 1536 + (nparts * nrhs * 16 + 255) // 256 * 256
+        assert lib.dirac_field_dot_workspace_bytes(C.byref(op)) == want
+    assert lib.dirac_field_dot_workspace_bytes(C.byref(_op(nrhs=0))) == abi.EINVAL
+    op = _op()
+    need = lib.dirac_field_dot_workspace_bytes(C.byref(op))
+    a, b, w = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
+    out = (C.c_double * 2)()
+    assert lib.dirac_field_dot(C.byref(op), a, b, w, need - 256, out, None) == abi.EWORKSPACE
+    assert lib.dirac_field_dot(C.byref(op), a, b, None, need, out, None) == abi.EINVAL
+    assert lib.dirac_field_dot(C.byref(op), a, b, C.c_void_p((3 << 20) + 16), need, out, None) == abi.EINVAL
+    assert lib.dirac_field_dot(C.byref(op), a, b, w, need, None, None) == abi.EINVAL
+    assert lib.dirac_field_dot(C.byref(op), a, b, C.c_void_p((1 << 20) + 4096), need, out, None) == abi.EINVAL
+
+
+def test_library_never_allocates_device_memory():
+    # every device buffer comes from the caller; no device-wide synchronisation
+    csrc = os.path.join(ROOT, "paper_1904_08616_amd", "csrc")
+    banned = re.compile(r"\b(hipMalloc\w*|hipFree\w*|hipExtMalloc\w*|hipMallocManaged|hipDeviceSynchronize)\s*\(")
+    hits = []
+    for name in sorted(os.listdir(csrc)):
+        text = open(os.path.join(csrc, name)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        hits += [f"{name}: {m.group(1)}" for m in banned.finditer(text)]
+    assert not hits, hits
+
+
 def test_bandwidth_probe_argument_checks():
     lib = abi.load()
     a, b = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
@@ -193,6 +228,38 @@ def test_launch_config_validation():
     assert got.xcd_remap == 7
     assert lib.dirac_multi_apply(0, None, None, None, None, 0, None) == abi.EINVAL
     assert lib.dirac_multi_apply(9, None, None, None, None, 0, None) == abi.EINVAL
+
+
+def test_tune_cache_entries_are_validated(tmp_path):
+    # the cache file is read once per process: a child process reads one with
+    # a valid entry, entries that do not fit their geometry, and one of an
+    # older format version (no GPU here, so the device name is "unknown")
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text(
+        "v2|unknown|4x4x4x4|p0|l18|n1 128 2 1 0 1 1 1 1\n"       # valid per-site entry
+        "v2|unknown|8x4x4x4|p0|l18|n1 96 1 1 0 0 1 1 1\n"        # block of 96 sites
+        "v2|unknown|16x16x16x16|p0|l18|n1 64 1 7 1 0 8 4 2\n"    # tile of 512 columns
+        "v2|unknown|6x4x4x4|p0|l18|n2 64 -2 1 0 0 1 1 1\n"       # split kernel with 2 sources
+        "v1|unknown|4x4x4x6|p0|l18|n1 128 2 1 0 1 1 1 1\n")      # older format
+    code = f"""
+import ctypes as C, sys
+sys.path.insert(0, {ROOT!r})
+from paper_1904_08616_amd import _abi as abi
+lib = abi.load()
+for dims, n in (((4, 4, 4, 4), 1), ((8, 4, 4, 4), 1), ((16, 16, 16, 16), 1), ((6, 4, 4, 4), 2), ((4, 4, 4, 6), 1)):
+    got = abi.DiracLaunch()
+    assert lib.dirac_launch_config(C.byref(abi.make_op(dims, 0, 18, n, 0.1)), C.byref(got)) == 0
+    print(got.tuned, got.block_sites, got.rhs_per_thread, got.tile_y)
+"""
+    env = dict(os.environ, DIRAC_TUNE_CACHE=str(cache))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.split()
+    rows = [lines[i:i + 4] for i in range(0, len(lines), 4)]
+    assert rows[0] == ["1", "128", "2", "1"]          # read back
+    assert all(r[0] == "0" for r in rows[1:]), rows   # rejected: the untuned default
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
