@@ -131,6 +131,20 @@ int64_t dirac_field_dot_workspace_bytes(const dirac_op* op);
 int dirac_field_dot(const dirac_op* op, const void* a_int, const void* b_int, void* work, int64_t work_bytes,
                     double* out_host, void* stream);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid allocation, callers without a workspace to hand):
+ * dirac_field_dot with its workspace in a fixed device array inside the
+ * library, 4 MiB per GPU, held from the first call on that GPU until the
+ * process ends.  Same kernels and result as dirac_field_dot; ops whose
+ * workspace (dirac_field_dot_workspace_bytes) exceeds the array, about
+ * 67 million sites x right-hand sides, are rejected with DIRAC_EINVAL.  The
+ * array is shared by every call on one GPU and keeps the last call's
+ * contents (each call overwrites what it reads); calls of one process are
+ * serialised by a lock held until the call's stream has synchronised, so
+ * they never overlap.  Allocates nothing and synchronises the stream. */
+int dirac_field_dot_noalloc(const dirac_op* op, const void* a_int, const void* b_int, double* out_host,
+                            void* stream);
+
 /* y = a x + y on internal fields of one precision, complex scalar a given by
  * (a_re, a_im), same for every right-hand side. */
 int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x_int, void* y_int,

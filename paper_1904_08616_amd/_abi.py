@@ -66,6 +66,7 @@ SIGNATURES = {
     "dirac_mdagm_apply": (C.c_int, [_OP, _P, _P, _P, _P, _P]),
     "dirac_field_dot_workspace_bytes": (C.c_int64, [_OP]),
     "dirac_field_dot": (C.c_int, [_OP, _P, _P, _P, C.c_int64, C.POINTER(C.c_double), _P]),
+    "dirac_field_dot_noalloc": (C.c_int, [_OP, _P, _P, C.POINTER(C.c_double), _P]),
     "dirac_field_axpy": (C.c_int, [_OP, C.c_double, C.c_double, _P, _P, _P]),
     "cg_workspace_bytes": (C.c_int64, [_OP, C.POINTER(CgParams)]),
     "cg_solve": (C.c_int, [_OP, _P, _P, _P, _P, _P, C.c_int64, C.POINTER(CgParams),

@@ -520,6 +520,63 @@ int dirac_field_dot(const dirac_op* op, const void* a, const void* b, void* work
   return DIRAC_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------ dot without allocation ---
+// dirac_field_dot_noalloc keeps the workspace of dirac_field_dot in this
+// fixed device array: each GPU the library runs on holds one copy until the
+// process ends.  Host code never passes `scratch` itself to a kernel or a
+// copy (in host code the name is only a stand-in for the device variable):
+// the device address comes from hipGetSymbolAddress, taken once per device
+// with that device current.
+constexpr int64_t kStaticScratchBytes = int64_t(4) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;           // one call at a time per process
+char* g_static_ptr[kMaxDevices];  // scratch's device address, per device
+
+int static_scratch(char** out) {
+  int dev = 0;
+  CHECK(hip_status(hipGetDevice(&dev), "hipGetDevice"));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(DIRAC_EUNSUPPORTED, "device %d out of range", dev);
+  if (g_static_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    CHECK(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+    if (p == nullptr || ((uintptr_t)p & 255u) != 0)
+      return set_error(DIRAC_EDEVICE, "scratch array has no aligned device address");
+    g_static_ptr[dev] = (char*)p;
+  }
+  *out = g_static_ptr[dev];
+  return DIRAC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dirac_field_dot_noalloc(const dirac_op* op, const void* a, const void* b, double* out_host, void* stream) {
+  clear_error();
+  const char* what = "dirac_field_dot_noalloc";
+  OpInfo o;
+  CHECK(check_op(op, &o, what));
+  CHECK(check_ptr(a, "a_int", what));
+  CHECK(check_ptr(b, "b_int", what));
+  if (out_host == nullptr) return set_error(DIRAC_EINVAL, "%s: out_host is NULL", what);
+  const int64_t need = dot_layout(o).total;
+  if (need > kStaticScratchBytes)
+    return set_error(DIRAC_EINVAL,
+                     "%s: this op needs %lld bytes of scratch, more than the fixed %lld-byte array "
+                     "(nrhs x sites up to about 67 million); use dirac_field_dot with a workspace",
+                     what, (long long)need, (long long)kStaticScratchBytes);
+  // The lock is held until the call's stream has synchronised, so calls of
+  // this process never use the array at the same time.
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  char* ptr = nullptr;
+  CHECK(static_scratch(&ptr));
+  return dirac_field_dot(op, a, b, ptr, kStaticScratchBytes, out_host, stream);
+}
+
 int dirac_field_axpy(const dirac_op* op, double a_re, double a_im, const void* x, void* y, void* stream) {
   clear_error();
   OpInfo o;

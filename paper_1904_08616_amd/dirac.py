@@ -159,6 +159,14 @@ class Operator:
         v = np.frombuffer(out, dtype=np.float64).copy()
         return v[0::2] + 1j * v[1::2]
 
+    def dot_noalloc(self, a, b):
+        """``dot`` through dirac_field_dot_noalloc (the library's fixed
+        scratch array; no workspace)."""
+        out = (C.c_double * (2 * self.nrhs))()
+        abi.check(self.lib.dirac_field_dot_noalloc(C.byref(self.op), _ptr(a), _ptr(b), out, _stream()))
+        v = np.frombuffer(out, dtype=np.float64).copy()
+        return v[0::2] + 1j * v[1::2]
+
     def axpy(self, a, x, y):
         a = complex(a)
         abi.check(self.lib.dirac_field_axpy(C.byref(self.op), a.real, a.imag, _ptr(x), _ptr(y), _stream()))

@@ -178,6 +178,24 @@ def test_field_dot_workspace_and_checks():
     assert lib.dirac_field_dot(C.byref(op), a, b, C.c_void_p((1 << 20) + 4096), need, out, None) == abi.EINVAL
 
 
+def test_field_dot_noalloc_limits():
+    # the fixed 4 MiB array holds the workspace of up to ~67 million
+    # site-sources; beyond that the call is refused before any device work
+    lib = abi.load()
+    out = (C.c_double * 24)()
+    big = _op(dims=(48, 48, 48, 64), nrhs=12)  # 85 million site-sources, a valid op
+    assert lib.dirac_field_dot_workspace_bytes(C.byref(big)) > 4 << 20
+    assert lib.dirac_field_dot_noalloc(C.byref(big), C.c_void_p(1 << 20), C.c_void_p(1 << 32), out, None) \
+        == abi.EINVAL
+    assert b"fixed" in lib.dirac_last_error()
+    fits = _op(dims=(32, 32, 32, 64), nrhs=12)  # the largest workload here: 25 million
+    assert lib.dirac_field_dot_workspace_bytes(C.byref(fits)) <= 4 << 20
+    z = C.c_void_p(0)
+    assert lib.dirac_field_dot_noalloc(C.byref(fits), z, z, out, None) == abi.EINVAL
+    assert lib.dirac_field_dot_noalloc(C.byref(fits), C.c_void_p(1 << 20), C.c_void_p(1 << 21), None, None) \
+        == abi.EINVAL
+
+
 def test_library_never_allocates_device_memory():
     # every device buffer comes from the caller; no device-wide synchronisation
     csrc = os.path.join(ROOT, "paper_1904_08616_amd", "csrc")
