@@ -58,3 +58,45 @@ def sample_sites(dims, k, seed=123):
 def at_sites(f, sites):
     s = np.asarray(sites)
     return f[..., s[:, 3], s[:, 2], s[:, 1], s[:, 0], :, :]
+
+
+def neighbourhood(dims, sites):
+    """The sites and their eight nearest neighbours (periodic), deduplicated."""
+    ext = np.array(dims)
+    out = [sites]
+    for mu in range(4):
+        for d in (1, -1):
+            s = sites.copy()
+            s[:, mu] = (s[:, mu] + d) % ext[mu]
+            out.append(s)
+    return np.unique(np.concatenate(out), axis=0)
+
+
+def sampled_residual(U, m, eta, x, sites, kind):
+    """Residual components of a solve at the sampled sites, by the oracle:
+    kind "ddagd" -> eta - D^dag D x (D x is needed on the sites'
+    neighbourhood only), "d" -> eta - D x, "ddag" -> eta - D^dag x."""
+    from oracle import wilson
+    at = (sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0])
+    if kind == "ddagd":
+        lx, ly, lz, lt = U.shape[3], U.shape[2], U.shape[1], U.shape[0]
+        nb = neighbourhood((lx, ly, lz, lt), sites)
+        y = np.zeros_like(x)
+        y[nb[:, 3], nb[:, 2], nb[:, 1], nb[:, 0]] = wilson.dslash_at(U, x, m, nb)
+        return eta[at] - wilson.dslash_at(U, y, m, sites, dagger=True)
+    return eta[at] - wilson.dslash_at(U, x, m, sites, dagger=(kind == "ddag"))
+
+
+def check_sampled_residual(name, U, m, eta, x, sites, kind, reported, tol=1e-10):
+    """||r|| <= tol ||eta|| bounds every component of r; the sampled mean of
+    |r|^2 scaled to the lattice estimates ||r||, which must agree with the
+    residual the library reported (within 3x: a sample of ~1000 sites)."""
+    V = int(np.prod(x.shape[:4]))
+    en = np.linalg.norm(eta.ravel())
+    r = sampled_residual(U, m, eta, x, sites, kind)
+    cmax = float(np.max(np.abs(r)))
+    est = np.sqrt(np.mean(np.sum(np.abs(r) ** 2, axis=(1, 2))) * V) / en
+    print(f"{name}: max |r_i| / |eta| {cmax / en:.2e}, sampled ||r||/||eta|| ~ {est:.2e}, reported {reported:.2e}")
+    assert cmax <= tol * en, name
+    assert est <= 3 * reported + 1e-14, name
+    return est
