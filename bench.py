@@ -1,20 +1,20 @@
 """Benchmark of the Wilson-Dirac hot path on one MI355X.
 
 Headline (one JSON line on stdout): float64 Wilson-Dirac application D of
-eq. (1) on the 16^3 x 32 lattice (U = exp(i 0.3 H) links, 18 reals per
-link, m_q = 0.05, seed 0), as algorithmic GB/s.  One step = one full-lattice
-D (both parities) on one of several resident copies of the inputs, rotated so
-that a step never finds its operands in the 256 MB last-level cache: the
-figure is an HBM figure.  Algorithmic bytes per site = 4 links x 144 B + one
-spinor read + one spinor written (960 B in float64, 18-real).
+eq. (1) on the 32^3 x 64 lattice (U = exp(i 0.3 H) links, 18 reals per
+link, m_q = 0.02, seed 0), as algorithmic GB/s.  One step = one full-lattice
+D (both parities).  A step moves 2.0 GB, eight times the 256 MB last-level
+cache, so the figure is an HBM figure.  Algorithmic bytes per site = 4 links
+x 144 B + one spinor read + one spinor written (960 B in float64, 18-real).
 
 The same line carries the roofline of that kernel (HIP events on the launch
-stream), the CPU oracle timed on a bounded sample of the same workload, and
-"extra" results: 12-real links, the HBM-bound 32^3 x 64 lattice in every
-precision, CG time-to-1e-10 (float64 vs Algorithm 1 mixed precision), the
-12-source and multi-lattice batches, the link force, BLAS-1, and the solve
-of D x = b through the even-odd Schur complement against CG on the normal
-equations of D.
+stream, and the HBM traffic from committed rocprofv3 counters), the CPU
+oracle timed on a bounded sample of the same workload (and of the other
+lattices), and "extra" results: 12-real links and the other precisions on
+32^3 x 64, the cache-resident 16^3 x 32 lattice, CG time-to-1e-10 (float64
+vs Algorithm 1 mixed precision), the 12-source and multi-lattice batches, the
+link force, BLAS-1, and the solve of D x = b through the even-odd Schur
+complement against CG on the normal equations of D.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 """
@@ -66,13 +66,15 @@ def kernel_name(prec, link, cfg, dims, dagger=False):
     return f"k_dslash<{args}, {cfg['rhs_per_thread']}> ({cfg['block_sites']} sites/block)"
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_f64_16x16x16x32_traffic.json")
+HEADLINE_DIMS = (32, 32, 32, 64)
+HEADLINE_MQ = 0.02
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_f64_32x32x32x64_traffic.json")
 
-# Streaming launches of the headline timed on rotated inputs beside the
-# autotuner's pick (tile_y x tile_z, t_chunk 2; the fastest cold in sweeps).
+# Streaming launches of the headline timed beside the autotuner's pick
+# (tile_y x tile_z, t_chunk, launch-order flags).
 HEADLINE_CANDIDATES = [
-    dict(block_sites=64, rhs_per_thread=1, xcd_remap=r, nt_store=1, lds=1, tile_y=ty, tile_z=tz, t_chunk=2)
-    for (ty, tz, r) in ((4, 4, 7), (8, 2, 1), (16, 1, 1), (4, 4, 1), (8, 2, 7))
+    dict(block_sites=64, rhs_per_thread=1, xcd_remap=r, nt_store=1, lds=1, tile_y=ty, tile_z=tz, t_chunk=tc)
+    for (ty, tz, tc, r) in ((4, 2, 16, 4), (4, 2, 8, 4), (8, 1, 16, 4), (2, 4, 16, 4), (4, 2, 16, 5))
 ]
 
 
@@ -532,38 +534,73 @@ def copy_at_size(torch, D, moved, copies, reps=200):
             "GB/s": round(2 * n / (ms * 1e-3) / 1e9, 1)}
 
 
-def cpu_baseline(dims, U, psi, m_q, budget_s=12.0):
-    """The oracle's D on the same lattice, timed on the host with one BLAS thread."""
+def _oracle_d_rate(wilson, U, psi, m_q, budget_s, min_runs=1, max_runs=5):
+    """Median seconds of the oracle's D over runs that fit ``budget_s`` (at
+    least ``min_runs``; the first is a warm-up when there is time for more)."""
+    t0 = time.perf_counter()
+    wilson.dslash(U, psi, m_q)
+    first = time.perf_counter() - t0
+    times = [first]
+    if first * 2 < budget_s:
+        times = []
+        while len(times) < max_runs and sum(times) + first < budget_s:
+            t0 = time.perf_counter()
+            wilson.dslash(U, psi, m_q)
+            times.append(time.perf_counter() - t0)
+    while len(times) < min_runs:
+        t0 = time.perf_counter()
+        wilson.dslash(U, psi, m_q)
+        times.append(time.perf_counter() - t0)
+    return float(np.median(times)), len(times)
+
+
+def cpu_baseline(dims, U, psi, m_q, budget_s=12.0, full=True):
+    """The oracle's D timed on the host with one BLAS thread: on the headline
+    lattice (the line's value), and with ``full`` on the other workloads'
+    lattices too (4^4, 16^3 x 32, 16^4, 24^3 x 48) plus its CG on 4^4 to
+    completion.  The oracle is plain NumPy, a correctness reference, not a
+    tuned CPU code."""
+    import synth
     from oracle import wilson
     try:
-        from threadpoolctl import threadpool_limits
+        from threadpoolctl import threadpool_info, threadpool_limits
     except ImportError:  # pragma: no cover
-        threadpool_limits = None
+        threadpool_limits = threadpool_info = None
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
-        wilson.dslash(U, psi, m_q)  # warm-up
-        n = 0
-        t0 = time.perf_counter()
-        while True:
-            wilson.dslash(U, psi, m_q)
-            n += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-        el = time.perf_counter() - t0
-        cg = oracle_small_cg()
+        blas = [dict(api=i.get("internal_api"), threads=i.get("num_threads")) for i in threadpool_info()] \
+            if threadpool_info else None
+        t_main, n_main = _oracle_d_rate(wilson, U, psi, m_q, budget_s)
+        V = int(np.prod(dims))
+        gbs = site_bytes("f64", 18) * V / t_main / 1e9
+        out = {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_main} full float64 applications of D on {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
+                         f"(median {t_main:.2f} s each; NumPy, one thread)",
+               "ms_per_step": round(1e3 * t_main, 1),
+               "gflops": round(FLOPS_PER_SITE * V / t_main / 1e9, 3)}
+        if full:
+            others = {}
+            for name, dd, kind, mq in (("4x4x4x4", (4, 4, 4, 4), "haar", 0.1),
+                                       ("16x16x16x32", (16, 16, 16, 32), "exp", 0.05),
+                                       ("16x16x16x16", (16, 16, 16, 16), "exp", 0.1),
+                                       ("24x24x24x48", (24, 24, 24, 48), "exp", 0.05)):
+                g = synth.rng(0)
+                Uo = synth.links_haar(dd, g) if kind == "haar" else synth.links_exp(dd, 0.3, g)
+                po = synth.spinor_gauss(dd, g)
+                t, n = _oracle_d_rate(wilson, Uo, po, mq, 3.0)
+                Vo = int(np.prod(dd))
+                others[f"dslash_{name}_f64"] = {
+                    "ms": round(1e3 * t, 2), "runs": n,
+                    "GB/s": round(site_bytes("f64", 18) * Vo / t / 1e9, 4),
+                    "GFLOP/s": round(FLOPS_PER_SITE * Vo / t / 1e9, 4)}
+            others["cg_4x4x4x4_m0.1"] = oracle_small_cg()
+            out["other_workloads"] = others
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
-    V = int(np.prod(dims))
-    gbs = site_bytes("f64", 18) * V * n / el / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} full float64 applications of D on {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
-                      f"({el:.1f} s, NumPy, one thread)",
-            "ms_per_step": round(1e3 * el / n, 2),
-            "gflops": round(FLOPS_PER_SITE * V * n / el / 1e9, 3),
-            "cg_4x4x4x4_m0.1": cg,
-            "host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
-            "cpu_model": cpu_model()}
+    out.update({"blas_threadpools": blas, "host_cpus": os.cpu_count(),
+                "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()})
+    return out
 
 
 def cpu_model():
@@ -643,11 +680,11 @@ def main(argv=None):
         res.update({m: solve_d_time(torch, D, big, Ub, pb, 0.02, m) for m in ("eo_f64", "eo_f16s")})
         print(json.dumps({"evenodd_32x32x32x64_m0.02": res}), flush=True)
         return 0
-    dims = (16, 16, 16, 32)
+    dims = HEADLINE_DIMS
     V = int(np.prod(dims))
-    m_q = 0.05
-    log("generating 16^3x32 inputs")
-    U, psi = gen_inputs(dims, seed=0)
+    m_q = HEADLINE_MQ
+    log("generating 32^3x64 inputs")
+    Ub, pb = gen_inputs(dims, seed=0)
 
     copy = copy_ceiling(torch, D, a.copy_gib) if a.copy_gib > 0 else None
 
@@ -658,13 +695,13 @@ def main(argv=None):
     fixed = rec["launch"] if rec is not None else None
     if a.headline_launch:
         fixed = json.loads(a.headline_launch)
-    log("headline: float64 Dslash 16^3x32, 18-real links")
-    ms, copies, cfg = time_dslash(torch, D, dims, "f64", 18, U, psi, a.steps, a.warmup, m_q=m_q, launch=fixed,
+    log("headline: float64 Dslash 32^3x64, 18-real links")
+    ms, copies, cfg = time_dslash(torch, D, dims, "f64", 18, Ub, pb, a.steps, a.warmup, m_q=m_q, launch=fixed,
                                   cold_candidates=HEADLINE_CANDIDATES)
     tuned = None
     if fixed is not None and not a.quick:
-        ms_t, _, cfg_t = time_dslash(torch, D, dims, "f64", 18, U, psi, a.steps, a.warmup, m_q=m_q,
-                                     force_tune=True)
+        ms_t, _, cfg_t = time_dslash(torch, D, dims, "f64", 18, Ub, pb, a.steps, a.warmup, m_q=m_q,
+                                     force_tune=True, cold_candidates=HEADLINE_CANDIDATES)
         tuned = {"ms": round(ms_t, 5), "GB/s": round(site_bytes("f64", 18) * V / (ms_t * 1e-3) / 1e9, 1),
                  "launch": cfg_t}
     bytes_per = site_bytes("f64", 18) * V
@@ -683,7 +720,7 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "wilson_dslash_16x16x16x32_f64",
+            "workload": "wilson_dslash_32x32x32x64_f64",
             "lattice": list(dims),
             "links": "exp(i*0.3*H), H Gaussian traceless Hermitian, seed 0, 18 reals per link",
             "source": "complex Gaussian spinor, seed 0",
@@ -710,7 +747,7 @@ def main(argv=None):
         line["roofline"]["traffic_over_algorithmic"] = round(traffic / bytes_per, 3)
     extra = {}
     if tuned is not None:
-        extra["dslash_16x16x16x32_f64_link18_autotuned"] = tuned
+        extra["dslash_32x32x32x64_f64_link18_autotuned"] = tuned
     if copy:
         extra["copy_ceiling"] = copy
         line["roofline"]["frac_of_copy"] = round(gbs / copy["GB/s"], 4)
@@ -719,31 +756,45 @@ def main(argv=None):
         line["roofline"]["frac_of_copy_at_headline_bytes"] = round(gbs / same["GB/s"], 4)
     if not a.quick:
         try:
-            ms12, _, cfg12 = time_dslash(torch, D, dims, "f64", 12, U, psi, a.steps, a.warmup, m_q=m_q)
-            b12 = site_bytes("f64", 12) * V
-            extra["dslash_16x16x16x32_f64_link12"] = {
-                "ms": round(ms12, 5), "GB/s": round(b12 / (ms12 * 1e-3) / 1e9, 1),
-                "frac": round(b12 / (ms12 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launch": cfg12}
-            log("CG 4^4: the single-launch iteration against the multi-kernel one")
-            extra["cg_4x4x4x4_m0.1_f64_link18"] = small_cg_time(torch, D)
-            log("CG 16^3x32 float64 vs mixed")
-            eta = psi
-            for inner, link in (("f64", 18), ("f64", 12), ("f32", 12), ("f16s", 12)):
-                extra[f"cg_16x16x16x32_m0.05_{inner}_link{link}"] = cg_time(torch, D, dims, U, eta, m_q, inner,
-                                                                            link=link)
-            big = (32, 32, 32, 64)
-            log("generating 32^3x64 inputs")
-            Ub, pb = gen_inputs(big, seed=0)
-            Vb = int(np.prod(big))
-            for prec, link in (("f64", 18), ("f64", 12), ("f32", 12), ("f16s", 12)):
+            for prec, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
                 log(f"Dslash 32^3x64 {prec}/{link}")
-                msb, cp, cfgb = time_dslash(torch, D, big, prec, link, Ub, pb, max(20, a.steps // 8), 5,
-                                            m_q=0.02)
-                bb = site_bytes(prec, link) * Vb
+                msb, _, cfgb = time_dslash(torch, D, dims, prec, link, Ub, pb, max(20, a.steps // 8), 5,
+                                           m_q=m_q)
+                bb = site_bytes(prec, link) * V
                 extra[f"dslash_32x32x32x64_{prec}_link{link}"] = {
                     "ms": round(msb, 4), "GB/s": round(bb / (msb * 1e-3) / 1e9, 1),
                     "frac": round(bb / (msb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                    "GFLOP/s": round(FLOPS_PER_SITE * Vb / (msb * 1e-3) / 1e9, 1), "launch": cfgb}
+                    "GFLOP/s": round(FLOPS_PER_SITE * V / (msb * 1e-3) / 1e9, 1), "launch": cfgb}
+            log("CG 32^3x64 m=0.02: float64 vs mixed")
+            for inner, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
+                extra[f"cg_32x32x32x64_m0.02_{inner}_link{link}"] = cg_time(torch, D, dims, Ub, pb, 0.02, inner,
+                                                                            link=link)
+            log("even-odd 32^3x64: Schur operator and the solve of D x = b")
+            for prec in ("f64", "f16s"):
+                extra[f"schur_32x32x32x64_{prec}_link12"] = time_schur(torch, D, dims, prec, 12, Ub, pb,
+                                                                       max(20, a.steps // 8), 0.02)
+            extra["solve_Dx=b_32x32x32x64_m0.02_link12"] = {
+                m: solve_d_time(torch, D, dims, Ub, pb, 0.02, m)
+                for m in ("ddagd_f64", "ddagd_f16s", "eo_f64", "eo_f32", "eo_f16s")}
+            torch.cuda.empty_cache()
+            # the cache-resident lattice (its D moves 126 MB, half the last-level cache)
+            small = (16, 16, 16, 32)
+            log("16^3x32 inputs")
+            U, psi = gen_inputs(small, seed=0)
+            Vs = int(np.prod(small))
+            for link in (18, 12):
+                mss, cps, cfgs = time_dslash(torch, D, small, "f64", link, U, psi, a.steps, a.warmup, m_q=0.05)
+                bs = site_bytes("f64", link) * Vs
+                extra[f"dslash_16x16x16x32_f64_link{link}"] = {
+                    "ms": round(mss, 5), "GB/s": round(bs / (mss * 1e-3) / 1e9, 1),
+                    "frac": round(bs / (mss * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "input_copies_rotated": cps,
+                    "launch": cfgs}
+            log("CG 4^4: the single-launch iteration against the multi-kernel one")
+            extra["cg_4x4x4x4_m0.1_f64_link18"] = small_cg_time(torch, D)
+            log("CG 16^3x32 float64 vs mixed")
+            for inner, link in (("f64", 18), ("f64", 12), ("f32", 12), ("f16s", 12)):
+                extra[f"cg_16x16x16x32_m0.05_{inner}_link{link}"] = cg_time(torch, D, small, U, psi, 0.05, inner,
+                                                                            link=link)
             # one GPU's share of 32^3x64 split in t over eight GPUs (periodic here,
             # so the t faces come from the same lattice instead of a neighbour)
             share = (32, 32, 32, 8)
@@ -755,18 +806,6 @@ def main(argv=None):
                 "ms": round(mss, 5), "GB/s": round(bs / (mss * 1e-3) / 1e9, 1),
                 "frac": round(bs / (mss * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launch": cfgs}
             del Us, ps
-            log("CG 32^3x64 m=0.02: float64 vs mixed")
-            for inner, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
-                extra[f"cg_32x32x32x64_m0.02_{inner}_link{link}"] = cg_time(torch, D, big, Ub, pb, 0.02, inner,
-                                                                            link=link)
-            log("even-odd 32^3x64: Schur operator and the solve of D x = b")
-            for prec in ("f64", "f16s"):
-                extra[f"schur_32x32x32x64_{prec}_link12"] = time_schur(torch, D, big, prec, 12, Ub, pb,
-                                                                       max(20, a.steps // 8), 0.02)
-            extra["solve_Dx=b_32x32x32x64_m0.02_link12"] = {
-                m: solve_d_time(torch, D, big, Ub, pb, 0.02, m)
-                for m in ("ddagd_f64", "ddagd_f16s", "eo_f64", "eo_f32", "eo_f16s")}
-            del Ub, pb
             torch.cuda.empty_cache()
             log("multi-RHS 24^3x48")
             extra.update(bench_multi_rhs(torch, D, a.steps, a.warmup))
@@ -783,8 +822,7 @@ def main(argv=None):
         line["extra"] = extra
     if not a.no_cpu:
         log("CPU oracle baseline")
-        U, psi = gen_inputs(dims, seed=0)
-        line["cpu_baseline"] = cpu_baseline(dims, U, psi, m_q)
+        line["cpu_baseline"] = cpu_baseline(dims, Ub, pb, m_q, full=not a.quick)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -7,8 +7,8 @@ import json
 import bench
 from paper_1904_08616_amd import profile_summary
 
-LAUNCH = {"block_sites": 64, "rhs_per_thread": 1, "xcd_remap": 7, "nt_store": 1, "lds": 1, "tile_y": 4,
-          "tile_z": 4, "t_chunk": 2, "tuned": 1}
+LAUNCH = {"block_sites": 64, "rhs_per_thread": 1, "xcd_remap": 4, "nt_store": 1, "lds": 1, "tile_y": 4,
+          "tile_z": 2, "t_chunk": 16, "tuned": 1}
 KERNEL = "void dirac::k_dslash_stream<0, 0, 18, false, 0, 256>(dirac::DslashArgs)"
 
 
@@ -23,24 +23,24 @@ def fake_record(tmp_path, monkeypatch, sha="abc"):
 def test_traffic_reported_for_the_profiled_kernel_and_launch(tmp_path, monkeypatch):
     fake_record(tmp_path, monkeypatch)
     monkeypatch.setattr(profile_summary, "kernel_sources_sha256", lambda names=None: "abc")
-    name = bench.kernel_name("f64", 18, LAUNCH, (16, 16, 16, 32))
+    name = bench.kernel_name("f64", 18, LAUNCH, bench.HEADLINE_DIMS)
     assert bench.counter_traffic(name, LAUNCH) == 1.5e8
-    other = dict(LAUNCH, t_chunk=4)
-    assert bench.counter_traffic(bench.kernel_name("f64", 18, other, (16, 16, 16, 32)), other) is None
-    assert bench.counter_traffic(bench.kernel_name("f64", 12, LAUNCH, (16, 16, 16, 32)), LAUNCH) is None
+    other = dict(LAUNCH, t_chunk=8)
+    assert bench.counter_traffic(bench.kernel_name("f64", 18, other, bench.HEADLINE_DIMS), other) is None
+    assert bench.counter_traffic(bench.kernel_name("f64", 12, LAUNCH, bench.HEADLINE_DIMS), LAUNCH) is None
 
 
 def test_traffic_dropped_once_the_sources_change(tmp_path, monkeypatch):
     fake_record(tmp_path, monkeypatch)
     monkeypatch.setattr(profile_summary, "kernel_sources_sha256", lambda names=None: "changed")
     assert bench.profiled_record() is None
-    assert bench.counter_traffic(bench.kernel_name("f64", 18, LAUNCH, (16, 16, 16, 32)), LAUNCH) is None
+    assert bench.counter_traffic(bench.kernel_name("f64", 18, LAUNCH, bench.HEADLINE_DIMS), LAUNCH) is None
 
 
 def test_committed_record_names_the_headline_kernel():
     with open(bench.TRAFFIC_RECORD) as f:
         rec = json.load(f)
     assert rec["launch"] is not None
-    name = bench.kernel_name("f64", 18, rec["launch"], (16, 16, 16, 32)).split(" (")[0]
+    name = bench.kernel_name("f64", 18, rec["launch"], bench.HEADLINE_DIMS).split(" (")[0]
     assert name in rec["FETCH_SIZE"]["kernel"] and name in rec["WRITE_SIZE"]["kernel"]
-    assert rec["traffic_bytes"] > bench.site_bytes("f64", 18) * 16 ** 3 * 32
+    assert rec["traffic_bytes"] > bench.site_bytes("f64", 18) * 32 ** 3 * 64
