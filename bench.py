@@ -71,10 +71,12 @@ HEADLINE_MQ = 0.02
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_f64_32x32x32x64_traffic.json")
 
 # Streaming launches of the headline timed beside the autotuner's pick
-# (tile_y x tile_z, t_chunk, launch-order flags).
+# (tile_y x tile_z, t_chunk, launch-order flags; flag 8: loads one direction
+# ahead), the fastest in sweeps on 32^3 x 64.
 HEADLINE_CANDIDATES = [
     dict(block_sites=64, rhs_per_thread=1, xcd_remap=r, nt_store=1, lds=1, tile_y=ty, tile_z=tz, t_chunk=tc)
-    for (ty, tz, tc, r) in ((4, 2, 16, 4), (4, 2, 8, 4), (8, 1, 16, 4), (2, 4, 16, 4), (4, 2, 16, 5))
+    for (ty, tz, tc, r) in ((4, 2, 32, 1), (4, 2, 32, 9), (4, 2, 16, 4), (4, 2, 16, 12), (4, 2, 32, 3),
+                            (4, 1, 32, 9), (8, 1, 32, 9))
 ]
 
 

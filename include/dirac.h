@@ -341,16 +341,18 @@ int dirac_plan_destroy(void* plan);
  *     each block of 64 sites, one direction pair per wave, partial spinors
  *     combined in LDS (nrhs = 1; for lattices too small to fill the device);
  *   - t-streaming (lds = 1): a block owns all of x times tile_y rows times
- *     tile_z planes (32 to 256 columns, in a block of 128 or 256 threads)
- *     and walks t_chunk time slices; the current slice is staged in LDS and
- *     the t neighbours stay in registers (tile_y | Ly and tile_z | Lz; one
- *     block per tile and right-hand side, the blocks of a tile adjacent so
- *     that they share its links in the L2).
+ *     tile_z planes (32 to 512 columns, float64 up to 256, in a block of
+ *     128, 256 or 512 threads) and walks t_chunk time slices; the current
+ *     slice is staged in LDS and the t neighbours stay in registers
+ *     (tile_y | Ly and tile_z | Lz; one block per tile and right-hand side,
+ *     the blocks of a tile adjacent so that they share its links in the L2).
  * xcd_remap orders tiles so that each XCD sweeps one contiguous region
  * (0 or 1).  For the t-streaming kernel it is a mask: bit 0 that XCD order,
  * bit 1 t-chunks fastest in the block order, bit 2 odd t-chunks walk down in
  * t, so that neighbouring chunks read their shared halo slice at the same
- * time.  nt_store writes the output with non-temporal stores. */
+ * time; bit 3 (float64 only) requests each direction's links and spinors one
+ * direction ahead of its hops, so that two directions' loads are in flight.
+ * nt_store writes the output with non-temporal stores. */
 typedef struct dirac_launch {
   int32_t block_sites;
   int32_t rhs_per_thread;

@@ -110,7 +110,7 @@ static std::vector<DslashEntry>& dslash_entries() {
 int run_dslash(int pin, int pout, int link, int dag, int epi, const LaunchCfg& c, DslashArgs a,
                hipStream_t st) {
   // the streaming kernel takes tiles that divide the lattice (one block per tile and rhs)
-  const bool stream = c.lds && stream_fits(a.g, c.sy, c.sz, c.tc);
+  const bool stream = c.lds && stream_fits(a.g, c.sy, c.sz, c.tc, pin);
   const int key = stream ? 0 : (c.lds ? 1 : c.R);
   for (const DslashEntry& e : dslash_entries()) {
     if (e.pin == pin && e.pout == pout && e.link == link && e.dag == dag && e.epi == epi && e.rpt == key) {
@@ -184,11 +184,13 @@ std::string cfg_key(const OpInfo& o) {
 
 // Whether launch configuration c fits geometry g with nrhs right-hand sides
 // (nullptr) or why not; normalises the fields the chosen kernel ignores.
-const char* check_cfg(const Geom& g, int nrhs, LaunchCfg& c) {
+const char* check_cfg(const Geom& g, int nrhs, int prec, LaunchCfg& c) {
   if (c.lds) {
-    if (c.remap < 0 || c.remap > 7) return "xcd_remap of the streaming kernel is a 3-bit mask";
-    if (!stream_fits(g, c.sy, c.sz, c.tc))
-      return "the streaming tile must divide the lattice and have 32 to 256 columns, t_chunk >= 1";
+    if (c.remap < 0 || c.remap > (prec == DIRAC_F64 ? 15 : 7))
+      return "xcd_remap of the streaming kernel is a 3-bit mask (float64: 4 bits)";
+    if (!stream_fits(g, c.sy, c.sz, c.tc, prec))
+      return "the streaming tile must divide the lattice and have 32 to 512 columns (float64: 256), "
+             "t_chunk >= 1";
     c.S = 64;
     c.R = 1;
     c.lds = 1;
@@ -206,8 +208,9 @@ const char* check_cfg(const Geom& g, int nrhs, LaunchCfg& c) {
 
 namespace {
 
-// Geometry and nrhs of a cache key (see cfg_key); false if it does not parse.
-bool parse_key(const char* key, Geom* g, int* nrhs) {
+// Geometry, nrhs and precision of a cache key (see cfg_key); false if it
+// does not parse.
+bool parse_key(const char* key, Geom* g, int* nrhs, int* prec) {
   int v = 0, L[4], p = 0, l = 0, n = 0;
   const char* q = std::strchr(key, '|');
   if (std::sscanf(key, "v%d|", &v) != 1 || v != kCfgVersion || q == nullptr) return false;
@@ -219,6 +222,7 @@ bool parse_key(const char* key, Geom* g, int* nrhs) {
   if (n < 1 || n > kMaxRhs) return false;
   *g = make_geom(L);
   *nrhs = n;
+  *prec = p;
   return true;
 }
 
@@ -236,8 +240,8 @@ void load_cache_file_locked() {
   while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds, &c.nt, &c.sy, &c.sz,
                      &c.tc) == 9) {
     Geom g;
-    int nrhs = 0;
-    if (!parse_key(key, &g, &nrhs) || check_cfg(g, nrhs, c) != nullptr) continue;
+    int nrhs = 0, prec = 0;
+    if (!parse_key(key, &g, &nrhs, &prec) || check_cfg(g, nrhs, prec, c) != nullptr) continue;
     c.tuned = 1;
     g_cfg[key] = c;
   }
@@ -777,10 +781,10 @@ static std::vector<LaunchCfg> stream_candidates(const OpInfo& o) {
     for (int sz = 1; sz <= o.g.Z; ++sz) {
       if (o.g.Z % sz) continue;
       const int n = stream_columns(o.g, sy, sz);
-      if (n > 256 || 4 * n < 3 * stream_block(o.g, sy, sz)) continue;
-      for (int tc : {1, 2, 4, 8, 16}) {
+      if (n > stream_max_columns(o.prec) || 4 * n < 3 * stream_block(o.g, sy, sz)) continue;
+      for (int tc : {1, 2, 4, 8, 16, 32}) {
         if (tc > o.g.T) continue;
-        if (!stream_fits(o.g, sy, sz, tc)) continue;
+        if (!stream_fits(o.g, sy, sz, tc, o.prec)) continue;
         v.push_back(LaunchCfg{64, 1, 1, 1, 0, sy, sz, tc, 1});
       }
     }
@@ -817,7 +821,7 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
         }
   // streaming kernel: XCD order, t-chunks fastest, alternating walk (bits 0..2)
   for (const LaunchCfg& c0 : stream_candidates(o))
-    for (int remap = 0; remap < 8; ++remap)
+    for (int remap = 0; remap < (o.prec == DIRAC_F64 ? 16 : 8); ++remap)
       for (int nt : {0, 1}) {
         LaunchCfg c = c0;
         c.remap = remap;
@@ -880,7 +884,7 @@ int dirac_set_launch_config(const dirac_op* op, const dirac_launch* cfg) {
   if (cfg == nullptr) return set_error(DIRAC_EINVAL, "dirac_set_launch_config: cfg is NULL");
   LaunchCfg c{cfg->block_sites, cfg->rhs_per_thread, cfg->xcd_remap, cfg->lds ? 1 : 0,
               cfg->nt_store, cfg->tile_y, cfg->tile_z, cfg->t_chunk, 1};
-  if (const char* why = check_cfg(o.g, o.nrhs, c))
+  if (const char* why = check_cfg(o.g, o.nrhs, o.prec, c))
     return set_error(DIRAC_EINVAL, "dirac_set_launch_config: %s (tile %d x %d x %d, t_chunk %d)", why, o.g.X,
                      cfg->tile_y, cfg->tile_z, cfg->t_chunk);
   store_cfg(o, c, false);

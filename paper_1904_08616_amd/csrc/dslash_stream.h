@@ -80,10 +80,57 @@ __device__ __forceinline__ void hop_apply(const M3<R>& u, const Cx<R> (&v)[12], 
 #define DIRAC_STREAM_WAVES_F32 3
 #endif
 
+// LDS bytes of the streaming kernel per block of NC threads: two slice
+// buffers and, in float64, the carried hops.
+template <int PI, int NC>
+constexpr size_t stream_lds_bytes() {
+  using R = typename SpinFmt<PI>::R;
+  return (size_t)NC * (PI == DIRAC_F64 ? 30 : 24) * sizeof(Cx<R>);
+}
+
 // Launch-order flags of the streaming kernel (DslashArgs::remap bits).
 constexpr int kStreamXcd = 1;   // XCD-contiguous block order
 constexpr int kStreamTFast = 2; // t-chunks fastest in the block order
 constexpr int kStreamAlt = 4;   // odd t-chunks walk downwards
+constexpr int kStreamPipe = 8;  // float64: loads one direction ahead (stream_walk's PIPE)
+
+// Store the output o of site (p, i) of right-hand side rhs, with the
+// epilogue EPI: plain store, store and |o|^2 (of the value as stored), or
+// dst = src - c o and |dst|^2 (c = the CG step alpha or 1).
+template <int PO, int EPI>
+__device__ __forceinline__ void stream_epilogue(const DslashArgs& a, int rhs, int p, int i,
+                                                const Cx<typename SpinFmt<PO>::R> (&o)[12], double& val) {
+  using SO = SpinFmt<PO>;
+  using Ro = typename SO::R;
+  const int Vh = a.g.Vh;
+  const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
+  if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
+    Cx<Ro> q[12];  // the value as stored
+    if (a.nt_store)
+      SO::template store_q<2>(orsrc, Vh, p, i, o, q);
+    else
+      SO::template store_q<0>(orsrc, Vh, p, i, o, q);
+    if constexpr (EPI == kEpiStoreNorm) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < 12; ++k) sum += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+      val += sum;
+    }
+  } else {
+    const Ro cf = a.sub_alpha ? (Ro)a.red.state[rhs].alpha : Ro(1);
+    Cx<Ro> d[12];
+    SO::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      d[k].re = fma(-cf, o[k].re, d[k].re);
+      d[k].im = fma(-cf, o[k].im, d[k].im);
+      sum += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+    }
+    SO::template store<0>(orsrc, Vh, p, i, d);
+    val += sum;
+  }
+}
 
 // One block's walk over the slices [t0, t1) of its tile, upwards (DOWN =
 // false) or downwards.  The t-link between the centre slice t and the next
@@ -276,41 +323,234 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
 #pragma unroll
     for (int k = 0; k < 12; ++k)
       o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
-    const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
-    if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
-      Cx<Ro> q[12];  // the value as stored
-      if (a.nt_store)
-        SO::template store_q<2>(orsrc, Vh, p, i, o, q);
-      else
-        SO::template store_q<0>(orsrc, Vh, p, i, o, q);
-      if constexpr (EPI == kEpiStoreNorm) {
-        double sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) sum += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
-        val += sum;
-      }
-    } else {
-      const Ro cf = a.sub_alpha ? (Ro)a.red.state[rhs].alpha : Ro(1);
-      Cx<Ro> d[12];
-      SO::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
-      double sum = 0.0;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        d[k].re = fma(-cf, o[k].re, d[k].re);
-        d[k].im = fma(-cf, o[k].im, d[k].im);
-        sum += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
-      }
-      SO::template store<0>(orsrc, Vh, p, i, d);
-      val += sum;
-    }
+    stream_epilogue<PO, EPI>(a, rhs, p, i, o, val);
     }  // act
     __syncthreads();  // slice tn complete; slice t no longer read
   }
 }
 
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC>
+// Links and face spinors of one direction's two hops, loaded one direction
+// ahead of the hops that use them (see stream_walk).
+template <int PI, int LK>
+struct DirLoads {
+  using Rl = typename SpinFmt<PI>::R;
+  M3<Rl> uf, ub;          // U_mu(n) and U_mu(n - mu)
+  Cx<Rl> vf[12], vb[12];  // psi(n + mu), psi(n - mu) where they lie outside the tile
+};
+
+// stream_walk with each step as a software pipeline over the directions:
+// the links of direction mu + 1 (and its neighbour spinors outside the tile)
+// are requested before the hops of direction mu are computed, so that two
+// directions' loads are in flight while the wave computes, instead of one
+// round trip to memory per direction.  It needs about twice the registers
+// (float64: VGPRs and AGPRs of a wave running alone on its SIMD, which the
+// LDS of a float64 walk imposes anyway).
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN>
+__device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, bool act, int x, int y, int z, int yl,
+                                            int zl, int t0, int t1, char* lds_raw, double& val) {
+  using SI = SpinFmt<PI>;
+  using SO = SpinFmt<PO>;
+  using LF = LinkFmt<PI, LK>;
+  using Rl = typename SI::R;
+  using Ro = typename SO::R;
+  constexpr int S = DAG ? -1 : 1;
+  constexpr int SC = DOWN ? -S : S;  // projector sign of the carried hop
+  const Geom g = a.g;
+  const int Vh = g.Vh;
+  const int BY = a.sy, BZ = a.sz;
+  const int tid = threadIdx.x;
+  const Rsrc Ur = make_rsrc(a.U, a.U_bytes);
+  const Rsrc in = make_rsrc(a.in + (size_t)rhs * a.in_stride, a.field_bytes);
+  const int xp = (x + 1 == g.X) ? 0 : x + 1, xm = (x == 0) ? g.X - 1 : x - 1;
+  const int yp = (y + 1 == g.Y) ? 0 : y + 1, ym = (y == 0) ? g.Y - 1 : y - 1;
+  const int zp = (z + 1 == g.Z) ? 0 : z + 1, zm = (z == 0) ? g.Z - 1 : z - 1;
+  const int col_xp = tid - x + xp, col_xm = tid - x + xm;
+  const bool in_yp = yl + 1 < BY, in_ym = yl > 0, in_zp = zl + 1 < BZ, in_zm = zl > 0;
+  // Lexicographic offsets of this thread's (x, y, z) column and of its
+  // spatial neighbours within one time slice; a site's index is then
+  // (t * X*Y*Z + column) / 2, with t uniform over the block.  Every +-1
+  // neighbour has the other parity (all extents are even).
+  const int cpar = (x + y + z) & 1;
+  const int ccol = (z * g.Y + y) * g.X + x;
+  const int ccol_xm = ccol - x + xm;
+  const int ccol_yp = ccol + (yp - y) * g.X, ccol_ym = ccol + (ym - y) * g.X;
+  const int ccol_zp = ccol + (zp - z) * g.X * g.Y, ccol_zm = ccol + (zm - z) * g.X * g.Y;
+  const int slice = g.X * g.Y * g.Z;
+  auto at = [&](int col, int par, int t, int& p, int& i) {
+    p = (par + t) & 1;
+    i = (t * slice + col) >> 1;
+  };
+  // LDS: two slice buffers [2][12][NC] (slice t is read while the next one
+  // is written) and, in float64, a private slot per thread for the carried hop.
+  Cx<Rl>* const lbase = reinterpret_cast<Cx<Rl>*>(lds_raw);
+  Cx<Rl>* const wslot = lbase + 24 * NC + tid;
+  constexpr bool kWtInLds = (PI == DIRAC_F64);
+  const int ts = DOWN ? t1 - 1 : t0;  // first centre slice
+  const int nsteps = t1 - t0;
+
+  // prologue: centre psi(ts) into buffer 0 and the hop carried into ts from
+  // the slice before it in walking order, kept as w = U^(dag) h (12 reals)
+  Cx<Rl> Wt[2][3];
+  if (act) {
+    int p, i;
+    at(ccol, cpar, ts, p, i);
+    Cx<Rl> v[12];
+    SI::load(in, Vh, p, i, v);
+    StreamLds<PI, NC>{lbase}.put(tid, v);
+    const int tq = DOWN ? ((ts + 1 == g.T) ? 0 : ts + 1) : ((ts == 0) ? g.T - 1 : ts - 1);
+    int pq, iq;
+    at(ccol, cpar, tq, pq, iq);
+    SI::load(in, Vh, pq, iq, v);
+    M3<Rl> u;
+    Cx<Rl> h[2][3];
+    project<3, SC>(v, h);
+    if constexpr (DOWN) {
+      LF::load(Ur, Vh, p, 3, i, u);  // U_t(ts) links ts and ts + 1
+      su3_mul(u, h, Wt);
+    } else {
+      LF::load(Ur, Vh, pq, 3, iq, u);  // U_t(ts - 1) links ts - 1 and ts
+      su3_dag_mul(u, h, Wt);
+    }
+    if constexpr (kWtInLds) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
+    }
+  }
+  __syncthreads();
+
+#pragma nounroll
+  for (int s = 0; s < nsteps; ++s) {
+    const int t = DOWN ? ts - s : ts + s;
+    const int b = s & 1;
+    const StreamLds<PI, NC> cur_s{lbase + b * 12 * NC};        // slice t
+    const StreamLds<PI, NC> nxt_s{lbase + (b ^ 1) * 12 * NC};  // slice tn
+    if (act) {
+    int p, i;
+    at(ccol, cpar, t, p, i);
+    const int tn = DOWN ? ((t == 0) ? g.T - 1 : t - 1) : ((t + 1 == g.T) ? 0 : t + 1);
+    int pn, in_;
+    at(ccol, cpar, tn, pn, in_);
+    int pxb, ixb, pyf, iyf, pyb, iyb, pzf, izf, pzb, izb;
+    at(ccol_xm, cpar ^ 1, t, pxb, ixb);
+    at(ccol_yp, cpar ^ 1, t, pyf, iyf);
+    at(ccol_ym, cpar ^ 1, t, pyb, iyb);
+    at(ccol_zp, cpar ^ 1, t, pzf, izf);
+    at(ccol_zm, cpar ^ 1, t, pzb, izb);
+
+    // requests of one direction: its two links and its neighbour spinors
+    // outside the tile
+    auto req_y = [&](DirLoads<PI, LK>& d) {
+      LF::load(Ur, Vh, p, 1, i, d.uf);
+      LF::load(Ur, Vh, pyb, 1, iyb, d.ub);
+      if (!in_yp) SI::load(in, Vh, pyf, iyf, d.vf);
+      if (!in_ym) SI::load(in, Vh, pyb, iyb, d.vb);
+    };
+    auto req_z = [&](DirLoads<PI, LK>& d) {
+      LF::load(Ur, Vh, p, 2, i, d.uf);
+      LF::load(Ur, Vh, pzb, 2, izb, d.ub);
+      if (!in_zp) SI::load(in, Vh, pzf, izf, d.vf);
+      if (!in_zm) SI::load(in, Vh, pzb, izb, d.vb);
+    };
+    auto req_t = [&](M3<Rl>& u) {  // U_t(n - t) walking down, U_t(n) walking up
+      if constexpr (DOWN)
+        LF::load(Ur, Vh, pn, 3, in_, u);
+      else
+        LF::load(Ur, Vh, p, 3, i, u);
+    };
+    // psi(tn) and the x links first
+    Cx<Rl> nxt[12];
+    SI::load(in, Vh, pn, in_, nxt);
+    M3<Rl> uxf, uxb;
+    LF::load(Ur, Vh, p, 0, i, uxf);
+    LF::load(Ur, Vh, pxb, 0, ixb, uxb);
+    DirLoads<PI, LK> dy, dz;
+    M3<Rl> ut;
+    req_y(dy);
+
+    Cx<Rl> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {Rl(0), Rl(0)};
+    if constexpr (kWtInLds) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Wt[k / 3][k % 3] = wslot[k * NC];
+    }
+    reconstruct_add<3, SC>(acc, Wt);  // the t hop carried from the previous slice
+    {
+      Cx<Rl> v[12];
+      // x: both neighbours are in the tile (it spans all of x)
+      cur_s.get(col_xp, v);
+      hop_apply<0, DAG, true, SI::kScaled>(uxf, v, acc);
+      cur_s.get(col_xm, v);
+      hop_apply<0, DAG, false, SI::kScaled>(uxb, v, acc);
+      nxt_s.put(tid, nxt);  // psi(tn) waits in LDS for the t hop and the next step
+      pin12(acc);
+      req_z(dz);
+      // y
+      if (in_yp) {
+        cur_s.get(tid + g.X, v);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = dy.vf[k];
+      }
+      hop_apply<1, DAG, true, SI::kScaled>(dy.uf, v, acc);
+      if (in_ym) {
+        cur_s.get(tid - g.X, v);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = dy.vb[k];
+      }
+      hop_apply<1, DAG, false, SI::kScaled>(dy.ub, v, acc);
+      pin12(acc);
+      req_t(ut);
+      // z
+      if (in_zp) {
+        cur_s.get(tid + g.X * BY, v);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = dz.vf[k];
+      }
+      hop_apply<2, DAG, true, SI::kScaled>(dz.uf, v, acc);
+      if (in_zm) {
+        cur_s.get(tid - g.X * BY, v);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = dz.vb[k];
+      }
+      hop_apply<2, DAG, false, SI::kScaled>(dz.ub, v, acc);
+      pin12(acc);
+      // t: the hop from psi(tn) now, and the hop from psi(t) carried to tn
+      nxt_s.get(tid, v);
+      hop_apply<3, DAG, !DOWN, SI::kScaled>(ut, v, acc);
+      cur_s.get(tid, v);
+      Cx<Rl> h[2][3];
+      project<3, SC>(v, h);
+      if constexpr (DOWN)
+        su3_mul(ut, h, Wt);
+      else
+        su3_dag_mul(ut, h, Wt);
+      if constexpr (kWtInLds) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
+      }
+    }
+
+    // output of site (p, i) with centre psi(t)
+    Cx<Rl> cur[12];
+    cur_s.get(tid, cur);
+    const Rl m4 = (Rl)a.mass4;
+    Cx<Ro> o[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      o[k] = {(Ro)fma(m4, cur[k].re, Rl(0.5) * acc[k].re), (Ro)fma(m4, cur[k].im, Rl(0.5) * acc[k].im)};
+    stream_epilogue<PO, EPI>(a, rhs, p, i, o, val);
+    }  // act
+    __syncthreads();  // slice tn complete; slice t no longer read
+  }
+}
+
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool PIPE = false>
 __global__ void __launch_bounds__(NC)
-__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? 2 : DIRAC_STREAM_WAVES_F32)))
+__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? (PIPE ? 1 : 2) : DIRAC_STREAM_WAVES_F32)))
 k_dslash_stream(DslashArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   const Geom g = a.g;
@@ -347,39 +587,70 @@ k_dslash_stream(DslashArgs a) {
   if (a.gate == kGateActive) on = a.red.state[rhs].active != 0;
   double vals[1][1] = {{0.0}};
   if (on) {
-    if ((a.remap & kStreamAlt) && (tt & 1))
-      stream_walk<PI, PO, LK, DAG, EPI, NC, true>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
-    else
-      stream_walk<PI, PO, LK, DAG, EPI, NC, false>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+    const bool down = (a.remap & kStreamAlt) && (tt & 1);
+    if constexpr (PIPE) {
+      if (down)
+        stream_walk_pipe<PI, PO, LK, DAG, EPI, NC, true>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+      else
+        stream_walk_pipe<PI, PO, LK, DAG, EPI, NC, false>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+    } else {
+      if (down)
+        stream_walk<PI, PO, LK, DAG, EPI, NC, true>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+      else
+        stream_walk<PI, PO, LK, DAG, EPI, NC, false>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+    }
   }
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, l, a.ntiles);
 }
 
 // Tile/geometry check of the streaming kernel (host): the tile's y and z
 // extents divide the lattice's, and its X * tile_y * tile_z columns fit a
-// block of 128 or 256 threads (32 to 256 columns; spare threads idle).
+// block of 128, 256 or 512 threads (32 to 512 columns, spare threads idle;
+// float64 up to 256 columns: the two slice buffers of 512 would not fit the
+// LDS of a CU).
+inline int stream_max_columns(int prec) { return prec == DIRAC_F64 ? 256 : 512; }
 inline int stream_columns(const Geom& g, int sy, int sz) { return g.X * sy * sz; }
-inline int stream_block(const Geom& g, int sy, int sz) { return stream_columns(g, sy, sz) <= 128 ? 128 : 256; }
-inline bool stream_fits(const Geom& g, int sy, int sz, int tc) {
+inline int stream_block(const Geom& g, int sy, int sz) {
+  const int n = stream_columns(g, sy, sz);
+  return n <= 128 ? 128 : (n <= 256 ? 256 : 512);
+}
+inline bool stream_fits(const Geom& g, int sy, int sz, int tc, int prec) {
   if (sy < 1 || sz < 1 || tc < 1) return false;
   if (g.Y % sy || g.Z % sz) return false;
   const int n = stream_columns(g, sy, sz);
-  return n >= 32 && n <= 256;
+  return n >= 32 && n <= stream_max_columns(prec);
 }
 
 template <int PI, int PO, int LK, bool DAG, int EPI>
 hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
-  if (!stream_fits(a.g, a.sy, a.sz, a.tc) || a.nrhs < 1) return hipErrorInvalidValue;
+  if (!stream_fits(a.g, a.sy, a.sz, a.tc, PI) || a.nrhs < 1) return hipErrorInvalidValue;
   const int nty = a.g.Y / a.sy, ntz = a.g.Z / a.sz, ntt = (a.g.T + a.tc - 1) / a.tc;
   a.ntiles = nty * ntz * ntt;
   a.ngroups = 1;
   const int nc = stream_block(a.g, a.sy, a.sz);
-  const size_t lds = (size_t)nc * (PI == DIRAC_F64 ? 30 : 24) * sizeof(Cx<typename SpinFmt<PI>::R>);
   const dim3 grid(a.ntiles * a.nrhs);
-  if (nc == 256)
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), grid, dim3(256), lds, st, a);
+  if constexpr (PI != DIRAC_F64) {
+    if (nc == 512) {
+      hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 512>), grid, dim3(512),
+                         (stream_lds_bytes<PI, 512>()), st, a);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess || EPI == kEpiStore) return e;
+      return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);
+    }
+  }
+  const bool pipe = PI == DIRAC_F64 && (a.remap & kStreamPipe);
+  if (nc == 256 && pipe)
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256, PI == DIRAC_F64>), grid, dim3(256),
+                       (stream_lds_bytes<PI, 256>()), st, a);
+  else if (nc == 256)
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), grid, dim3(256),
+                       (stream_lds_bytes<PI, 256>()), st, a);
+  else if (pipe)
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128, PI == DIRAC_F64>), grid, dim3(128),
+                       (stream_lds_bytes<PI, 128>()), st, a);
   else
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128>), grid, dim3(128), lds, st, a);
+    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128>), grid, dim3(128),
+                       (stream_lds_bytes<PI, 128>()), st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || EPI == kEpiStore) return e;
   return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);

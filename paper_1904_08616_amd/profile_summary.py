@@ -10,8 +10,9 @@
         same counters read for the largest plain copy in the run, as HBM bytes
 
 The copy is the runtime's buffer copy (torch's device-to-device copy of a
-known size): its read and write volumes are known, so (known KiB) / (counted
-KiB) is the factor that turns a counter into bytes on this chip.
+known size, --copy-gib): its read and write volumes are known, so (known
+KiB) / (counted KiB) is the factor that turns a counter into bytes on this
+chip.  It must be the largest buffer copy in the run.
 """
 
 from __future__ import annotations
@@ -65,7 +66,7 @@ def trace_report(db, command):
     return "\n".join(out)
 
 
-def counter_report(fetch_db, write_db, kernel, fetch_cmd, write_cmd):
+def counter_report(fetch_db, write_db, kernel, fetch_cmd, write_cmd, copy_gib=1.0):
     res = {}
     lines = [f"FETCH_SIZE command: {fetch_cmd}", f"WRITE_SIZE command: {write_cmd}", ""]
     for db, name in ((fetch_db, "FETCH_SIZE"), (write_db, "WRITE_SIZE")):
@@ -74,7 +75,7 @@ def counter_report(fetch_db, write_db, kernel, fetch_cmd, write_cmd):
         if not copies:
             raise SystemExit(f"{db}: no buffer copy to calibrate {name} against")
         cmax = max(r[4] for r in copies)  # KiB counted for the largest copy
-        known = 1 << 20  # the copy moves 1 GiB each way
+        known = copy_gib * (1 << 20)  # KiB the calibration copy moves each way
         scale = known / cmax
         ks = [r for r in rows if kernel in r[0]]
         if not ks:
@@ -84,7 +85,7 @@ def counter_report(fetch_db, write_db, kernel, fetch_cmd, write_cmd):
                      "copy_kib_per_gib": cmax, "scale": scale, "bytes": k[2] * scale * 1024}
         lines.append(f"{name}: {k[0]}")
         lines.append(f"  dispatches {k[1]}, KiB per dispatch avg {k[2]:.1f} (min {k[3]:.1f}, max {k[4]:.1f})")
-        lines.append(f"  a 1 GiB copy counts {cmax:.1f} KiB -> scale {scale:.5f}; "
+        lines.append(f"  a {copy_gib:g} GiB copy counts {cmax:.1f} KiB -> scale {scale:.5f}; "
                      f"bytes per dispatch {k[2] * scale * 1024:.4e}")
     total = res["FETCH_SIZE"]["bytes"] + res["WRITE_SIZE"]["bytes"]
     lines.append(f"HBM bytes per dispatch (scaled FETCH + WRITE): {total:.4e}")
@@ -119,6 +120,9 @@ def main(argv=None):
     c.add_argument("--write-command", required=True)
     c.add_argument("--json")
     c.add_argument("--launch", help="launch configuration (JSON) the counters were taken with")
+    c.add_argument("--copy-gib", type=float, default=1.0,
+                   help="size of the calibration copy (the largest buffer copy in the runs; it must be larger "
+                        "than any other device copy there, such as clones of the inputs)")
     q = sub.add_parser("pmc")
     q.add_argument("dbs", nargs="+")
     q.add_argument("--command", required=True)
@@ -130,7 +134,7 @@ def main(argv=None):
     if a.mode == "pmc":
         print(pmc_report(a.dbs, a.command, a.kernel))
         return 0
-    text, res = counter_report(a.fetch, a.write, a.kernel, a.fetch_command, a.write_command)
+    text, res = counter_report(a.fetch, a.write, a.kernel, a.fetch_command, a.write_command, a.copy_gib)
     print(text)
     if a.json:
         res["kernel_sources_sha256"] = kernel_sources_sha256()

@@ -230,7 +230,11 @@ def test_launch_config_validation():
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 3, 1, 1, 0))) == abi.EINVAL
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 1, 1, 2, 0))) == abi.EINVAL
     op16 = _op(dims=(16, 16, 16, 16))
+    assert lib.dirac_set_launch_config(C.byref(op16), C.byref(L(64, 1, 1, 0, 1, 8, 8, 2, 0))) == abi.EINVAL
+    # 512 columns: 32- and 16-bit formats only
     assert lib.dirac_set_launch_config(C.byref(op16), C.byref(L(64, 1, 1, 0, 1, 8, 4, 2, 0))) == abi.EINVAL
+    op16f = _op(dims=(16, 16, 16, 16), prec=abi.F32, link=abi.LINK12)
+    assert lib.dirac_set_launch_config(C.byref(op16f), C.byref(L(64, 1, 1, 0, 1, 8, 4, 2, 0))) == abi.OK
     assert lib.dirac_set_launch_config(C.byref(op), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
     op8 = _op(dims=(8, 4, 4, 4))
     assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 1, 0, 1, 4, 4, 2, 0))) == abi.OK
@@ -239,11 +243,14 @@ def test_launch_config_validation():
     got = abi.DiracLaunch()
     assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
     assert (got.lds, got.tile_y, got.tile_z, got.t_chunk, got.tuned) == (1, 4, 4, 2, 1)
-    # the streaming kernel's order flags are a 3-bit mask
-    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 8, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
-    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 7, 0, 1, 4, 4, 2, 0))) == abi.OK
+    # the streaming kernel's order flags are a 3-bit mask, 4 bits in float64
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 16, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 15, 0, 1, 4, 4, 2, 0))) == abi.OK
     assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
-    assert got.xcd_remap == 7
+    assert got.xcd_remap == 15
+    op8f = _op(dims=(8, 4, 4, 4), prec=abi.F32, link=abi.LINK12)
+    assert lib.dirac_set_launch_config(C.byref(op8f), C.byref(L(64, 1, 8, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op8f), C.byref(L(64, 1, 7, 0, 1, 4, 4, 2, 0))) == abi.OK
     assert lib.dirac_multi_apply(0, None, None, None, None, 0, None) == abi.EINVAL
     assert lib.dirac_multi_apply(9, None, None, None, None, 0, None) == abi.EINVAL
 
@@ -258,7 +265,7 @@ def test_tune_cache_entries_are_validated(tmp_path):
     cache.write_text(
         "v2|unknown|4x4x4x4|p0|l18|n1 128 2 1 0 1 1 1 1\n"       # valid per-site entry
         "v2|unknown|8x4x4x4|p0|l18|n1 96 1 1 0 0 1 1 1\n"        # block of 96 sites
-        "v2|unknown|16x16x16x16|p0|l18|n1 64 1 7 1 0 8 4 2\n"    # tile of 512 columns
+        "v2|unknown|16x16x16x16|p0|l18|n1 64 1 7 1 0 8 8 2\n"    # tile of 1024 columns
         "v2|unknown|6x4x4x4|p0|l18|n2 64 -2 1 0 0 1 1 1\n"       # split kernel with 2 sources
         "v1|unknown|4x4x4x6|p0|l18|n1 128 2 1 0 1 1 1 1\n")      # older format
     code = f"""

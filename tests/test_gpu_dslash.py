@@ -11,6 +11,7 @@ import torch
 
 import synth
 from oracle import lowprec, wilson
+from paper_1904_08616_amd import _abi as abi
 from paper_1904_08616_amd import dirac as D
 from tests.gpu_helpers import at_sites, cuda, host, inputs, rel_inf, sample_sites
 
@@ -272,8 +273,8 @@ def test_split_kernel_parity(prec, link, tol, dagger):
 
 
 STREAM_CASES = [
-    # dims, (tile_y, tile_z), t_chunk    (tile = all of x times tile_y times tile_z: 32 to 256
-    # columns in a block of 128 or 256 threads; spare threads idle)
+    # dims, (tile_y, tile_z), t_chunk    (tile = all of x times tile_y times tile_z: 32 to 512
+    # columns in a block of 128, 256 or 512 threads; spare threads idle)
     ((12, 6, 4, 6), (2, 2), 2),    # 48 of 128 threads
     ((24, 4, 6, 4), (2, 3), 3),    # 144 of 256 threads, ragged chunk
     ((6, 4, 4, 4), (4, 4), 1),     # 96 columns, one tile spans y and z
@@ -285,6 +286,11 @@ STREAM_CASES = [
     ((16, 4, 8, 6), (2, 8), 6),    # one chunk covers all of t
     ((32, 4, 4, 4), (2, 2), 2),
     ((32, 4, 4, 4), (4, 2), 1),
+    # 512 threads (32- and 16-bit formats)
+    ((32, 4, 4, 6), (4, 4), 4),    # 512 columns, ragged last chunk
+    ((16, 8, 8, 6), (8, 4), 2),    # faces in z only
+    ((24, 4, 6, 4), (2, 6), 3),    # 288 of 512 threads
+    ((16, 8, 8, 4), (4, 8), 4),    # one chunk covers all of t
 ]
 
 
@@ -300,8 +306,14 @@ def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
     pi = op.pack_spinor(cuda(psi))
     f = wilson.dslash_dagger if dagger else wilson.dslash
     ref = f(lowprec.store_links(U, prec), lowprec.store(psi, prec), m)
-    # remap bits: XCD order, t-chunks fastest, odd chunks walking down in t
-    for remap in range(8):
+    # remap bits: XCD order, t-chunks fastest, odd chunks walking down in t,
+    # and in float64 loads one direction ahead; float64 tiles stop at 256
+    # columns (two slice buffers of 512 exceed the LDS)
+    if prec == "f64" and dims[0] * tile[0] * tile[1] > 256:
+        with pytest.raises(abi.DiracError):
+            op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc)
+        return
+    for remap in range(16 if prec == "f64" else 8):
         op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc, xcd_remap=remap)
         assert op.launch_config()["lds"] == 1
         got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
