@@ -54,12 +54,15 @@ def site_bytes(prec, link, nrhs=1):
 def kernel_name(prec, link, cfg, dims, dagger=False):
     """Which Dslash kernel a launch configuration selects, as rocprofv3 names it
     (template arguments: input/output precision, link reals, dagger, epilogue,
-    then rhs per thread, waves per site or threads per block)."""
+    then rhs per thread, waves per site, or threads per block and whether
+    the walk requests loads one direction ahead)."""
     P = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}[prec]
     args = f"{P}, {P}, {link}, {'true' if dagger else 'false'}, 0"
     if cfg["lds"]:
-        nc = dims[0] * cfg["tile_y"] * cfg["tile_z"]
-        return (f"k_dslash_stream<{args}, {nc}> (tile all-x * {cfg['tile_y']} * {cfg['tile_z']}, "
+        cols = dims[0] * cfg["tile_y"] * cfg["tile_z"]
+        nc = 128 if cols <= 128 else (256 if cols <= 256 else 512)
+        pipe = "true" if prec == "f64" and cfg["xcd_remap"] & 8 else "false"
+        return (f"k_dslash_stream<{args}, {nc}, {pipe}> (tile all-x * {cfg['tile_y']} * {cfg['tile_z']}, "
                 f"t_chunk {cfg['t_chunk']})")
     if cfg["rhs_per_thread"] < 0:
         return f"k_dslash_split<{args}, {-cfg['rhs_per_thread']}> ({cfg['block_sites']} sites/block)"
