@@ -761,7 +761,7 @@ def main(argv=None):
         line["roofline"]["frac_of_copy_at_headline_bytes"] = round(gbs / same["GB/s"], 4)
     if not a.quick:
         try:
-            for prec, link in (("f64", 12), ("f32", 12), ("f16s", 12)):
+            for prec, link in (("f64", 12), ("f32", 12), ("f32", 10), ("f16s", 12), ("f16s", 10)):
                 log(f"Dslash 32^3x64 {prec}/{link}")
                 msb, _, cfgb = time_dslash(torch, D, dims, prec, link, Ub, pb, max(20, a.steps // 8), 5,
                                            m_q=m_q)

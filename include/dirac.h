@@ -55,11 +55,20 @@ extern "C" {
  * Every global reduction accumulates in float64 in all precisions. */
 enum { DIRAC_F64 = 0, DIRAC_F32 = 1, DIRAC_F16S = 2, DIRAC_BF16S = 3 };
 
-/* Link storage: the full 3x3 complex matrix (18 reals) or its first two rows
- * (12 reals) with row 2 = conj(row0 x row1) rebuilt in registers (exact for
- * SU(3); the paper trades link words for arithmetic in the same way, section
- * "Larger Lattice Streamed from the DDR Memory").  F16S/BF16S need LINK12. */
-enum { DIRAC_LINK18 = 18, DIRAC_LINK12 = 12 };
+/* Link storage: the full 3x3 complex matrix (18 reals); its first two rows
+ * (12 reals) with row 2 = conj(row0 x row1) rebuilt in registers; or the
+ * 10-real form: row 0 and, for the pivot column k (the row-0 entry of
+ * smallest modulus, lowest index on ties), U_1k and U_2k, the other four
+ * entries rebuilt from the cofactor identity conj(U_ij) = cofactor_ij of a
+ * special unitary matrix (a division by 1 - |U_0k|^2 >= 2/3, no
+ * trigonometric function).  All are exact for SU(3) up to rounding; the
+ * paper streams 10-parameter links and trades link words for arithmetic in
+ * the same way (section "Larger Lattice Streamed from the DDR Memory").
+ * F16S/BF16S need LINK12, or LINK10 (F16S); LINK10 is built for F32 and
+ * F16S and for the Dslash calls (dirac_apply, dirac_dagger_apply,
+ * dirac_mdagm_apply, dirac_autotune); the solver, even-odd and
+ * multi-lattice calls return DIRAC_EUNSUPPORTED for it. */
+enum { DIRAC_LINK18 = 18, DIRAC_LINK12 = 12, DIRAC_LINK10 = 10 };
 
 enum {
   DIRAC_OK = 0,
@@ -76,7 +85,7 @@ enum {
 typedef struct dirac_op {
   int32_t L[4];   /* Lx, Ly, Lz, Lt: each even and >= 2, V = product < 2^31 */
   int32_t prec;   /* DIRAC_F64 / F32 / F16S / BF16S */
-  int32_t link;   /* DIRAC_LINK18 / DIRAC_LINK12 */
+  int32_t link;   /* DIRAC_LINK18 / DIRAC_LINK12 / DIRAC_LINK10 */
   int32_t nrhs;   /* 1..12 right-hand sides stored one after another */
   int32_t flags;  /* 0 */
   double m_q;     /* quark mass, finite */

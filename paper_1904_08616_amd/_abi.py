@@ -12,7 +12,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdirac.so")
 
 F64, F32, F16S, BF16S = 0, 1, 2, 3
-LINK18, LINK12 = 18, 12
+LINK18, LINK12, LINK10 = 18, 12, 10
 OK, EINVAL, EDEVICE, ENOCONV, EBREAKDOWN, EUNSUPPORTED, EWORKSPACE = 0, -1, -2, -3, -4, -5, -6
 
 STATUS_NAMES = {

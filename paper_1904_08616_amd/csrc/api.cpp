@@ -56,10 +56,12 @@ int check_op(const dirac_op* op, OpInfo* o, const char* what) {
     if (V >= (int64_t(1) << 31)) return set_error(DIRAC_EINVAL, "%s: lattice volume must be < 2^31", what);
   }
   if (!valid_prec(op->prec)) return set_error(DIRAC_EINVAL, "%s: unknown precision %d", what, op->prec);
-  if (op->link != DIRAC_LINK18 && op->link != DIRAC_LINK12)
-    return set_error(DIRAC_EINVAL, "%s: link must be 18 or 12 (got %d)", what, op->link);
-  if ((op->prec == DIRAC_F16S || op->prec == DIRAC_BF16S) && op->link != DIRAC_LINK12)
-    return set_error(DIRAC_EUNSUPPORTED, "%s: F16S/BF16S need 12-real links", what);
+  if (op->link != DIRAC_LINK18 && op->link != DIRAC_LINK12 && op->link != DIRAC_LINK10)
+    return set_error(DIRAC_EINVAL, "%s: link must be 18, 12 or 10 (got %d)", what, op->link);
+  if ((op->prec == DIRAC_F16S || op->prec == DIRAC_BF16S) && op->link == DIRAC_LINK18)
+    return set_error(DIRAC_EUNSUPPORTED, "%s: F16S/BF16S need 12- or 10-real links", what);
+  if (op->link == DIRAC_LINK10 && op->prec != DIRAC_F32 && op->prec != DIRAC_F16S)
+    return set_error(DIRAC_EUNSUPPORTED, "%s: 10-real links are built for F32 and F16S", what);
   if (op->nrhs < 1 || op->nrhs > kMaxRhs)
     return set_error(DIRAC_EINVAL, "%s: nrhs must be in 1..%d (got %d)", what, kMaxRhs, op->nrhs);
   if (!std::isfinite(op->m_q)) return set_error(DIRAC_EINVAL, "%s: m_q must be finite", what);

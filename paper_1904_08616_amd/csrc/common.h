@@ -162,6 +162,48 @@ template <class R> __device__ __forceinline__ void su3_row2_fma(M3<R>& u, R zero
   u.e[2][2] = cr(u.e[0][0], u.e[1][1], u.e[0][1], u.e[1][0]);
 }
 
+// Squared modulus of a complex entry, evaluated the same way by the link
+// packer and the 10-real rebuild (their pivot choices must agree).
+template <class R> __device__ __forceinline__ R abs2_exact(Cx<R> a) { return fma(a.re, a.re, a.im * a.im); }
+
+// Rows 1 and 2 of an SU(3) matrix from row 0 (in u.e[0]) and, for the pivot
+// column k, the entries b0 = U_1k and c0 = U_2k (the 10-real link form; the
+// paper streams a 10-parameter link and trades the two extra words against
+// trigonometric functions, Larger Lattice Streamed from the DDR Memory).
+// The pivot is the column whose row-0 entry has the smallest modulus (lowest
+// index on ties).  Rotating the columns cyclically by k gives V = U P, still
+// special unitary, whose entries satisfy conj(V_ij) = cofactor_ij; solved
+// for the four entries outside V's row 0 and column 0 they divide by
+// n = |V_01|^2 + |V_02|^2 = 1 - |V_00|^2 >= 2/3, and no modulus is taken
+// from a difference.
+template <class R>
+__device__ __forceinline__ void su3_from_row_pivot(M3<R>& u, Cx<R> b0, Cx<R> c0) {
+  const Cx<R> e0 = u.e[0][0], e1 = u.e[0][1], e2 = u.e[0][2];
+  const R m0 = abs2_exact(e0), m1 = abs2_exact(e1), m2 = abs2_exact(e2);
+  const bool k0 = m0 <= m1 && m0 <= m2;
+  const bool k1 = !k0 && m1 <= m2;
+  auto sel = [k0, k1](Cx<R> x0, Cx<R> x1, Cx<R> x2) { return k0 ? x0 : (k1 ? x1 : x2); };
+  const Cx<R> a0 = sel(e0, e1, e2), a1 = sel(e1, e2, e0), a2 = sel(e2, e0, e1);
+  const R n = k0 ? m1 + m2 : (k1 ? m2 + m0 : m0 + m1);
+  const R inv = R(1) / n;
+  // V_11 = -(conj(a0) a1 b0 + conj(a2) conj(c0)) / n
+  Cx<R> t = cmul(cmul(conj(a0), a1), b0);
+  t = cmadd(t, conj(a2), conj(c0));
+  const Cx<R> b1 = (-inv) * t;
+  // V_12 = (conj(a1) conj(c0) - conj(a0) a2 b0) / n
+  const Cx<R> b2 = inv * (cmul(conj(a1), conj(c0)) - cmul(cmul(conj(a0), a2), b0));
+  // V_21 = conj(a2) conj(b0) - conj(a0) conj(b2);  V_22 = conj(a0) conj(b1) - conj(a1) conj(b0)
+  const Cx<R> c1 = cmul(conj(a2), conj(b0)) - cmul(conj(a0), conj(b2));
+  const Cx<R> c2 = cmul(conj(a0), conj(b1)) - cmul(conj(a1), conj(b0));
+  // U_{r, k+j} = V_{r, j}
+  u.e[1][0] = sel(b0, b2, b1);
+  u.e[1][1] = sel(b1, b0, b2);
+  u.e[1][2] = sel(b2, b1, b0);
+  u.e[2][0] = sel(c0, c2, c1);
+  u.e[2][1] = sel(c1, c0, c2);
+  u.e[2][2] = sel(c2, c1, c0);
+}
+
 // ------------------------------------------------------- storage formats --
 // Spinor fields: per right-hand side, [parity][NV][Vh] 16-byte vectors,
 // followed for scaled formats by a float scale per site [parity][Vh].
@@ -473,7 +515,8 @@ __host__ __device__ inline int64_t spinor_field_bytes(int prec, int64_t V) {
 }
 
 // Gauge links: [parity][mu][NL][Vh] vectors.  Entry k = 3*row + col of the
-// row-major colour matrix; LINK12 stores rows 0 and 1 only.
+// row-major colour matrix; LINK12 stores rows 0 and 1 only, LINK10 row 0 and
+// the pivot column's rows 1 and 2 (su3_from_row_pivot).
 //   F64 18: 9 double2     F64 12: 6 double2
 //   F32 18: 9 float2      F32 12: 3 float4 (two entries each)
 //   F16S/BF16S 12: 3 x (4 x 16-bit) = two entries each, unscaled
@@ -527,6 +570,27 @@ template <> struct LinkFmt<DIRAC_F32, 12> {
     su3_row2(u);
   }
 };
+// 10-real links (su3_from_row_pivot): per (parity, mu) block of 40 Vh bytes,
+// plane A = (U_00, U_01), plane B = (U_02, U_1k) as float4, plane C = U_2k
+// as float2.
+template <> struct LinkFmt<DIRAC_F32, 10> {
+  using R = float;
+  static constexpr int NL = 3;
+  static constexpr int kBytes = 40;
+  __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
+    const uint32_t blk = 40u * (uint32_t)Vh;  // bytes of one (parity, mu) block
+    const uint32_t po = plane_off(p, 4u * blk);
+    const uint32_t base = (uint32_t)mu * blk;
+    const float4 A = bld<float4>(U, (uint32_t)i * 16u + po, base);
+    const float4 B = bld<float4>(U, (uint32_t)i * 16u + po, base + 16u * (uint32_t)Vh);
+    const float2 C = bld<float2>(U, (uint32_t)i * 8u + po, base + 32u * (uint32_t)Vh);
+    u.e[0][0] = {A.x, A.y};
+    u.e[0][1] = {A.z, A.w};
+    u.e[0][2] = {B.x, B.y};
+    su3_from_row_pivot(u, Cx<R>{B.z, B.w}, Cx<R>{C.x, C.y});
+  }
+};
+
 template <bool BF> struct LinkHalf12 {
   using R = float;
   static constexpr int NL = 3;
@@ -548,6 +612,27 @@ template <bool BF> struct LinkHalf12 {
 };
 template <> struct LinkFmt<DIRAC_F16S, 12> : LinkHalf12<false> {};
 template <> struct LinkFmt<DIRAC_BF16S, 12> : LinkHalf12<true> {};
+
+// 10-real 16-bit links: per (parity, mu) block of 20 Vh bytes, plane A =
+// (U_00, U_01, U_02, U_1k) as 8 x 16 bits, plane B = U_2k as 2 x 16 bits.
+struct LinkHalf10 {
+  using R = float;
+  static constexpr int NL = 2;
+  static constexpr int kBytes = 20;
+  __device__ static __forceinline__ float dec(unsigned short h) { return h_to_f(h); }
+  __device__ static __forceinline__ void load(Rsrc U, int Vh, int p, int mu, int i, M3<R>& u) {
+    const uint32_t blk = 20u * (uint32_t)Vh;
+    const uint32_t po = plane_off(p, 4u * blk);
+    const uint32_t base = (uint32_t)mu * blk;
+    const uint4 A = bld<uint4>(U, (uint32_t)i * 16u + po, base);
+    const unsigned C = bld<unsigned>(U, (uint32_t)i * 4u + po, base + 16u * (uint32_t)Vh);
+    u.e[0][0] = {dec(A.x & 0xFFFFu), dec(A.x >> 16)};
+    u.e[0][1] = {dec(A.y & 0xFFFFu), dec(A.y >> 16)};
+    u.e[0][2] = {dec(A.z & 0xFFFFu), dec(A.z >> 16)};
+    su3_from_row_pivot(u, Cx<R>{dec(A.w & 0xFFFFu), dec(A.w >> 16)}, Cx<R>{dec(C & 0xFFFFu), dec(C >> 16)});
+  }
+};
+template <> struct LinkFmt<DIRAC_F16S, 10> : LinkHalf10 {};
 
 __host__ __device__ inline int64_t link_bytes(int prec, int link) {
   if (prec == DIRAC_F64) return link * 8;

@@ -115,6 +115,32 @@ __global__ void __launch_bounds__(kBlock) k_pack_gauge(Geom g, int nb, const dou
     if constexpr (P == DIRAC_F64) {
       double2* b = reinterpret_cast<double2*>(out) + ((size_t)(s.p * 4 + mu) * nent) * Vh + s.i;
       for (int k = 0; k < nent; ++k) b[k * Vh] = m[k];
+    } else if constexpr (LK == 10) {
+      // row 0 as stored, the pivot chosen on it as the rebuild chooses it
+      // (su3_from_row_pivot), then the pivot column's rows 1 and 2
+      auto enc = [](double x) -> unsigned { return (unsigned)f_to_h((float)x); };
+      Cx<float> r[3];
+      unsigned h[3] = {0u, 0u, 0u};
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (P == DIRAC_F32) {
+          r[c] = {(float)m[c].x, (float)m[c].y};
+        } else {
+          h[c] = enc(m[c].x) | (enc(m[c].y) << 16);
+          r[c] = {h_to_f(h[c] & 0xFFFFu), h_to_f(h[c] >> 16)};
+        }
+      }
+      const float m0 = abs2_exact(r[0]), m1 = abs2_exact(r[1]), m2 = abs2_exact(r[2]);
+      const int k = (m0 <= m1 && m0 <= m2) ? 0 : (m1 <= m2 ? 1 : 2);
+      const double2 bk = m[3 + k], ck = m[6 + k];
+      char* blk = out + (size_t)(s.p * 4 + mu) * (size_t)(LinkFmt<P, 10>::kBytes) * Vh;
+      if constexpr (P == DIRAC_F32) {
+        reinterpret_cast<float4*>(blk)[s.i] = make_float4(r[0].re, r[0].im, r[1].re, r[1].im);
+        reinterpret_cast<float4*>(blk + 16 * Vh)[s.i] = make_float4(r[2].re, r[2].im, (float)bk.x, (float)bk.y);
+        reinterpret_cast<float2*>(blk + 32 * Vh)[s.i] = make_float2((float)ck.x, (float)ck.y);
+      } else {
+        reinterpret_cast<uint4*>(blk)[s.i] = make_uint4(h[0], h[1], h[2], enc(bk.x) | (enc(bk.y) << 16));
+        reinterpret_cast<unsigned*>(blk + 16 * Vh)[s.i] = enc(ck.x) | (enc(ck.y) << 16);
+      }
     } else if constexpr (P == DIRAC_F32 && LK == 18) {
       float2* b = reinterpret_cast<float2*>(out) + ((size_t)(s.p * 4 + mu) * 9) * Vh + s.i;
       for (int k = 0; k < 9; ++k) b[k * Vh] = make_float2((float)m[k].x, (float)m[k].y);
@@ -440,6 +466,10 @@ hipError_t pack_gauge(const Geom& g, int prec, int link, const void* U, void* ou
     hipLaunchKernelGGL((k_pack_gauge<DIRAC_F32, 12>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, u, o);
   else if (prec == DIRAC_F16S && link == 12)
     hipLaunchKernelGGL((k_pack_gauge<DIRAC_F16S, 12>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, u, o);
+  else if (prec == DIRAC_F32 && link == 10)
+    hipLaunchKernelGGL((k_pack_gauge<DIRAC_F32, 10>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, u, o);
+  else if (prec == DIRAC_F16S && link == 10)
+    hipLaunchKernelGGL((k_pack_gauge<DIRAC_F16S, 10>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, u, o);
   else if (prec == DIRAC_BF16S && link == 12)
     hipLaunchKernelGGL((k_pack_gauge<DIRAC_BF16S, 12>), sg.grid, dim3(kBlock), 0, st, g, sg.nb, u, o);
   else

@@ -52,6 +52,9 @@ def test_sizes():
     assert lib.dirac_spinor_bytes(C.byref(_op(prec=abi.F16S, link=abi.LINK12))) == V * 52
     # right-hand sides are 256-byte aligned one after another
     assert lib.dirac_spinor_bytes(C.byref(_op(nrhs=12))) == 12 * V * 192
+    # 10-real links: 40 bytes (F32) or 20 bytes (F16S) per link
+    assert lib.dirac_gauge_bytes(C.byref(_op(prec=abi.F32, link=abi.LINK10))) == V * 160
+    assert lib.dirac_gauge_bytes(C.byref(_op(prec=abi.F16S, link=abi.LINK10))) == V * 80
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -60,8 +63,11 @@ def test_sizes():
     (dict(nrhs=0), abi.EINVAL),
     (dict(nrhs=13), abi.EINVAL),
     (dict(prec=7), abi.EINVAL),
-    (dict(link=10), abi.EINVAL),
+    (dict(link=11), abi.EINVAL),
     (dict(prec=abi.F16S, link=abi.LINK18), abi.EUNSUPPORTED),
+    (dict(prec=abi.F64, link=abi.LINK10), abi.EUNSUPPORTED),
+    (dict(prec=abi.BF16S, link=abi.LINK10), abi.EUNSUPPORTED),
+    (dict(link=8), abi.EINVAL),
     (dict(m_q=float("nan")), abi.EINVAL),
     (dict(dims=(2048, 1024, 1024, 2)), abi.EINVAL),           # volume 2^32 >= 2^31
     (dict(dims=(128, 128, 128, 4)), abi.EUNSUPPORTED),        # float64 18-real links 4.8 GB >= 4 GiB

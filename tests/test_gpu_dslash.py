@@ -53,15 +53,16 @@ def test_f64_gamma5_hermiticity_on_gpu():
     assert rel_inf(g5v(d), dd) <= 1e-13
 
 
-@pytest.mark.parametrize("prec,link,tol", [("f32", 18, 5e-6), ("f32", 12, 5e-6), ("f16s", 12, 1.5e-3),
-                                           ("bf16s", 12, 1.2e-2)])
+@pytest.mark.parametrize("prec,link,tol", [("f32", 18, 5e-6), ("f32", 12, 5e-6), ("f32", 10, 5e-6),
+                                           ("f16s", 12, 1.5e-3), ("f16s", 10, 1.5e-3), ("bf16s", 12, 1.2e-2)])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_low_precision_parity(prec, link, tol, dagger):
     dims = (8, 4, 6, 4)
     U, psi = inputs(dims, "exp", seed=3)
     m = 0.05
-    # oracle on the inputs as the format stores them, in float64 arithmetic
-    Ur = lowprec.store_links(U, prec)
+    # oracle on the inputs as the format stores them (links in the same 18-,
+    # 12- or 10-real form), in float64 arithmetic
+    Ur = lowprec.store_links(U, prec, link)
     pr = lowprec.store(psi, prec)
     ref = (wilson.dslash_dagger if dagger else wilson.dslash)(Ur, pr, m)
     got = _run(U, psi, m, prec, link, dagger)
@@ -249,7 +250,8 @@ def test_full_size_32x32x32x64_sampled():
 
 
 @pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
-                                           ("f16s", 12, 1.5e-3), ("bf16s", 12, 1.2e-2)])
+                                           ("f32", 10, 5e-6), ("f16s", 12, 1.5e-3), ("f16s", 10, 1.5e-3),
+                                           ("bf16s", 12, 1.2e-2)])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_split_kernel_parity(prec, link, tol, dagger):
     # direction-split variants (2 or 4 waves per 64-site block) against the
@@ -261,7 +263,7 @@ def test_split_kernel_parity(prec, link, tol, dagger):
     Ui = op.pack_gauge(cuda(U))
     pi = op.pack_spinor(cuda(psi))
     f = wilson.dslash_dagger if dagger else wilson.dslash
-    ref = f(lowprec.store_links(U, prec), lowprec.store(psi, prec), m)
+    ref = f(lowprec.store_links(U, prec, link), lowprec.store(psi, prec), m)
     op.set_launch_config(128, 1, 1, 0, 0)
     base = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
     for R in (-2, -4):
@@ -296,7 +298,8 @@ STREAM_CASES = [
 
 @pytest.mark.parametrize("dims,tile,tc", STREAM_CASES)
 @pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
-                                           ("f16s", 12, 1.5e-3), ("bf16s", 12, 1.2e-2)])
+                                           ("f32", 10, 5e-6), ("f16s", 12, 1.5e-3), ("f16s", 10, 1.5e-3),
+                                           ("bf16s", 12, 1.2e-2)])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
     U, psi = inputs(dims, "exp", seed=10)
@@ -305,7 +308,7 @@ def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
     Ui = op.pack_gauge(cuda(U))
     pi = op.pack_spinor(cuda(psi))
     f = wilson.dslash_dagger if dagger else wilson.dslash
-    ref = f(lowprec.store_links(U, prec), lowprec.store(psi, prec), m)
+    ref = f(lowprec.store_links(U, prec, link), lowprec.store(psi, prec), m)
     # remap bits: XCD order, t-chunks fastest, odd chunks walking down in t,
     # and in float64 loads one direction ahead; float64 tiles stop at 256
     # columns (two slice buffers of 512 exceed the LDS)
@@ -372,3 +375,30 @@ def test_full_size_12_point_sources_sampled():
         del out
     del Ui, pi
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_ten_real_links(prec):
+    # the 10-real form: the free field (identity links, where the division of
+    # the rebuild would vanish without the pivot) gives bitwise the result of
+    # the 12-real form; Haar links (any pivot column) and near-identity links
+    # match the oracle's emulation of the stored form; D^dag D as well
+    dims = (8, 4, 6, 6)
+    g = synth.rng(31)
+    psi = synth.spinor_gauss(dims, g)
+    m = 0.1
+    tol = 5e-6 if prec == "f32" else 1.5e-3
+    unit = synth.links_unit(dims)
+    d10 = _run(unit, psi, m, prec, 10, False)
+    assert np.array_equal(d10, _run(unit, psi, m, prec, 12, False))
+    for U in (synth.links_haar(dims, g), synth.links_exp(dims, 1e-4, g)):
+        for dagger in (False, True):
+            ref = (wilson.dslash_dagger if dagger else wilson.dslash)(lowprec.store_links(U, prec, 10),
+                                                                     lowprec.store(psi, prec), m)
+            assert rel_inf(_run(U, psi, m, prec, 10, dagger), ref) <= tol
+        op = D.Operator(dims, m, prec, 10)
+        Ui = op.pack_gauge(cuda(U))
+        got = host(op.unpack_spinor(op.mdagm(Ui, op.pack_spinor(cuda(psi)))))
+        Ur = lowprec.store_links(U, prec, 10)
+        ref = wilson.dslash_dagger(Ur, lowprec.store(wilson.dslash(Ur, lowprec.store(psi, prec), m), prec), m)
+        assert rel_inf(got, ref) <= 2 * tol

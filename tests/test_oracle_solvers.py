@@ -243,3 +243,61 @@ def test_mixed_cg_inner_cap_falls_back_for_bf16():
     omd = np.conj(np.swapaxes(om, -1, -2))
     xref = synth.gauge_transform_spinor(freefield.solve_ddagd(synth.gauge_transform_spinor(eta, omd), 0.05), om)
     assert np.linalg.norm((x - xref).ravel()) / np.linalg.norm(xref.ravel()) < freefield.condition_number(0.05) * 2e-10
+
+
+LINK_KINDS = ("haar", "exp", "exp_tiny", "unit", "pure_gauge")
+
+
+def _links(kind, dims, g):
+    if kind == "haar":
+        return synth.links_haar(dims, g)
+    if kind == "exp":
+        return synth.links_exp(dims, 0.3, g)
+    if kind == "exp_tiny":
+        return synth.links_exp(dims, 1e-6, g)
+    if kind == "unit":
+        return synth.links_unit(dims)
+    return synth.links_pure_gauge(synth.gauge_transform_haar(dims, g))
+
+
+@pytest.mark.parametrize("kind", LINK_KINDS)
+def test_ten_real_links_rebuild_su3(kind):
+    # the 10-real form (row 0 and the pivot column's rows 1 and 2) rebuilds
+    # special unitary matrices to float64 rounding for every kind of link,
+    # near-identity and free-field links included; the pivot's row-0 entry
+    # is the smallest of the row (N = 1 - |U_0k|^2 >= 2/3)
+    g = synth.rng(12)
+    U = _links(kind, (4, 2, 2, 2), g)
+    row0, k, col = lowprec.pack10(U)
+    assert np.allclose(row0, U[..., 0, :], rtol=0, atol=0)
+    mods = np.abs(U[..., 0, :]) ** 2
+    assert np.all(np.take_along_axis(mods, k[..., None], -1)[..., 0] <= mods.min(axis=-1) + 1e-15)
+    assert np.max(np.abs(lowprec.store_links(U, "f64", 10) - U)) < 2e-15
+
+
+@pytest.mark.parametrize("fmt,bound", [("f32", 3e-7), ("f16s", 1e-3), ("bf16s", 8e-3)])
+@pytest.mark.parametrize("kind", LINK_KINDS)
+def test_ten_real_links_format_bound(fmt, bound, kind):
+    # every stored entry carries one rounding of the format (half an ulp of
+    # 2^-24, 2^-11, 2^-8 at |U_ij| <= 1); the rebuilt ones stay within a few
+    g = synth.rng(14)
+    U = _links(kind, (4, 4, 2, 2), g)
+    err = np.max(np.abs(lowprec.store_links(U, fmt, 10) - U))
+    print(f"10-real {fmt} {kind}: max entry error {err:.2e}")
+    assert err < bound
+
+
+def test_eight_real_links_lose_accuracy_near_identity():
+    # Why the library stores 10 reals: an 8-real form (two entries kept only
+    # as phases) must take one modulus from 1 - |U_01|^2 - |U_02|^2.  With
+    # the pivot (smallest row-0 entry first) that difference cancels on
+    # near-identity links; without it, links with |U_00| = 1 (the free
+    # field) lose their 2x2 block.  The 10-real form has neither problem.
+    g = synth.rng(13)
+    U = synth.links_exp((4, 2, 2, 2), 1e-3, g)
+    err8 = np.max(np.abs(lowprec.store_links(U, "f32", 8) - U))
+    err10 = np.max(np.abs(lowprec.store_links(U, "f32", 10) - U))
+    assert err8 > 100 * err10 and err10 < 3e-7, (err8, err10)
+    with np.errstate(all="ignore"):
+        free = lowprec.store_links(synth.links_unit((2, 2, 2, 2)), "f64", 8, pivot=False)
+    assert not np.all(np.isfinite(free))
