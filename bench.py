@@ -60,7 +60,10 @@ def kernel_name(prec, link, cfg, dims, dagger=False):
     args = f"{P}, {P}, {link}, {'true' if dagger else 'false'}, 0"
     if cfg["lds"]:
         cols = dims[0] * cfg["tile_y"] * cfg["tile_z"]
-        nc = 128 if cols <= 128 else (256 if cols <= 256 else 512)
+        if prec == "f64":
+            nc = 128 if cols <= 128 else 256
+        else:
+            nc = next((b for b in (128, 192, 256, 384) if cols <= b), 512)
         pipe = "true" if prec == "f64" and cfg["xcd_remap"] & 8 else "false"
         return (f"k_dslash_stream<{args}, {nc}, {pipe}> (tile all-x * {cfg['tile_y']} * {cfg['tile_z']}, "
                 f"t_chunk {cfg['t_chunk']})")

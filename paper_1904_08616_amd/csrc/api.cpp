@@ -774,8 +774,8 @@ int dirac_plan_destroy(void* plan) {
 
 // ------------------------------------------------------------ tuning -----
 // Streaming-kernel tiles worth timing for this geometry: all of x times
-// tile_y x tile_z with tile_y | Ly, tile_z | Lz, filling at least 3/4 of a
-// block of 128 or 256 threads.
+// tile_y x tile_z with tile_y | Ly, tile_z | Lz, filling at least 3/4 of
+// their block.
 static std::vector<LaunchCfg> stream_candidates(const OpInfo& o) {
   std::vector<LaunchCfg> v;
   for (int sy = 1; sy <= o.g.Y; ++sy) {
@@ -783,7 +783,7 @@ static std::vector<LaunchCfg> stream_candidates(const OpInfo& o) {
     for (int sz = 1; sz <= o.g.Z; ++sz) {
       if (o.g.Z % sz) continue;
       const int n = stream_columns(o.g, sy, sz);
-      if (n > stream_max_columns(o.prec) || 4 * n < 3 * stream_block(o.g, sy, sz)) continue;
+      if (n > stream_max_columns(o.prec) || 4 * n < 3 * stream_block(o.g, sy, sz, o.prec)) continue;
       for (int tc : {1, 2, 4, 8, 16, 32}) {
         if (tc > o.g.T) continue;
         if (!stream_fits(o.g, sy, sz, tc, o.prec)) continue;

@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_cg_small(SmallCgArgs a) {
       Cx<Ro> q[12];  // the value as stored
       SO::store_q(tr, Vh, p, i, o, q);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+      for (int k = 0; k < 12; ++k) s = fma((double)o[k].im, (double)q[k].im, fma((double)o[k].re, (double)q[k].re, s));
     }
     s = wg_sum(s, red);  // its barriers also publish t to the workgroup
     if (!(s > 0.0) || !isfinite(s) || !isfinite(rho)) {
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_cg_small(SmallCgArgs a) {
       for (int k = 0; k < 12; ++k) {
         d[k].re = fma(-cf, (Rv)w[k].re, d[k].re);
         d[k].im = fma(-cf, (Rv)w[k].im, d[k].im);
-        s2 += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+        s2 = fma((double)d[k].im, (double)d[k].im, fma((double)d[k].re, (double)d[k].re, s2));
       }
       SV::store(rr, Vh, p, i, d);
     }

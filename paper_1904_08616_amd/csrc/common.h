@@ -107,9 +107,11 @@ template <class R> __device__ __forceinline__ Cx<R> mul_i(Cx<R> a) { return {-a.
 template <class R> __device__ __forceinline__ Cx<R> mul_mi(Cx<R> a) { return {a.im, -a.re}; }   // -i a
 template <class R> __device__ __forceinline__ Cx<R> neg(Cx<R> a) { return {-a.re, -a.im}; }
 template <class R> __device__ __forceinline__ Cx<R> conj(Cx<R> a) { return {a.re, -a.im}; }
-// a * b
+// a * b, each component one product and one fused multiply-add in a fixed
+// order, so that every kernel instance rounds it the same way (left to the
+// compiler, which product is fused may differ between instances)
 template <class R> __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+  return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
 // acc + a * b
 template <class R> __device__ __forceinline__ Cx<R> cmadd(Cx<R> acc, Cx<R> a, Cx<R> b) {
@@ -414,8 +416,13 @@ template <bool BF> struct SpinScaled {
       uint4 t = bld<uint4>(f, o, (uint32_t)k * (uint32_t)Vh * 16u);
       unsigned w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
         v[4 * k + j] = {s * dec((unsigned short)(w[j] & 0xFFFFu)), s * dec((unsigned short)(w[j] >> 16))};
+        // the products are final here: the compiler may not fuse them into
+        // the additions that follow (which it would do differently in
+        // different kernel instances)
+        asm("" : "+v"(v[4 * k + j].re), "+v"(v[4 * k + j].im));
+      }
     }
   }
   // The 24 stored values unscaled, and the site scale: load() is s * v.

@@ -196,7 +196,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int p, int i, i
         // 16-bit formats).
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+        for (int k = 0; k < 12; ++k) s = fma((double)o[k].im, (double)q[k].im, fma((double)o[k].re, (double)q[k].re, s));
         vals[r][0] = s;
       }
     } else {
@@ -208,7 +208,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int p, int i, i
       for (int k = 0; k < 12; ++k) {
         d[k].re = fma(-cf, o[k].re, d[k].re);
         d[k].im = fma(-cf, o[k].im, d[k].im);
-        s += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+        s = fma((double)d[k].im, (double)d[k].im, fma((double)d[k].re, (double)d[k].re, s));
       }
       SO::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, d);
       vals[r][0] = s;
@@ -361,7 +361,7 @@ k_dslash_split(DslashArgs a) {
         SO::round(q);
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+        for (int k = 0; k < 12; ++k) s = fma((double)o[k].im, (double)q[k].im, fma((double)o[k].re, (double)q[k].re, s));
         vals[0][0] = s;
       }
     } else {
@@ -375,7 +375,7 @@ k_dslash_split(DslashArgs a) {
       for (int k = 0; k < 12; ++k) {
         dd[k].re = fma(-cf, o[k].re, dd[k].re);
         dd[k].im = fma(-cf, o[k].im, dd[k].im);
-        s += (double)dd[k].re * dd[k].re + (double)dd[k].im * dd[k].im;
+        s = fma((double)dd[k].im, (double)dd[k].im, fma((double)dd[k].re, (double)dd[k].re, s));
       }
       SO::template store_range<0>(make_rsrc(a.out, a.out_bytes), Vh, p, i, dd, v0, v1);
       vals[0][0] = s;

@@ -113,7 +113,7 @@ __device__ __forceinline__ void stream_epilogue(const DslashArgs& a, int rhs, in
     if constexpr (EPI == kEpiStoreNorm) {
       double sum = 0.0;
 #pragma unroll
-      for (int k = 0; k < 12; ++k) sum += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+      for (int k = 0; k < 12; ++k) sum = fma((double)o[k].im, (double)q[k].im, fma((double)o[k].re, (double)q[k].re, sum));
       val += sum;
     }
   } else {
@@ -125,7 +125,7 @@ __device__ __forceinline__ void stream_epilogue(const DslashArgs& a, int rhs, in
     for (int k = 0; k < 12; ++k) {
       d[k].re = fma(-cf, o[k].re, d[k].re);
       d[k].im = fma(-cf, o[k].im, d[k].im);
-      sum += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+      sum = fma((double)d[k].im, (double)d[k].im, fma((double)d[k].re, (double)d[k].re, sum));
     }
     SO::template store<0>(orsrc, Vh, p, i, d);
     val += sum;
@@ -605,14 +605,18 @@ k_dslash_stream(DslashArgs a) {
 
 // Tile/geometry check of the streaming kernel (host): the tile's y and z
 // extents divide the lattice's, and its X * tile_y * tile_z columns fit a
-// block of 128, 256 or 512 threads (32 to 512 columns, spare threads idle;
-// float64 up to 256 columns: the two slice buffers of 512 would not fit the
-// LDS of a CU).
+// block of 128, 192, 256, 384 or 512 threads (32 to 512 columns, spare
+// threads idle; blocks of 192 and 384 fit tiles of a lattice 24 or 48 wide
+// in x without idle waves).  Float64 takes up to 256 columns in blocks of
+// 128 or 256: the two slice buffers of more would not fit the LDS of a CU.
 inline int stream_max_columns(int prec) { return prec == DIRAC_F64 ? 256 : 512; }
 inline int stream_columns(const Geom& g, int sy, int sz) { return g.X * sy * sz; }
-inline int stream_block(const Geom& g, int sy, int sz) {
+inline int stream_block(const Geom& g, int sy, int sz, int prec) {
   const int n = stream_columns(g, sy, sz);
-  return n <= 128 ? 128 : (n <= 256 ? 256 : 512);
+  if (prec == DIRAC_F64) return n <= 128 ? 128 : 256;
+  for (int b : {128, 192, 256, 384})
+    if (n <= b) return b;
+  return 512;
 }
 inline bool stream_fits(const Geom& g, int sy, int sz, int tc, int prec) {
   if (sy < 1 || sz < 1 || tc < 1) return false;
@@ -627,12 +631,19 @@ hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
   const int nty = a.g.Y / a.sy, ntz = a.g.Z / a.sz, ntt = (a.g.T + a.tc - 1) / a.tc;
   a.ntiles = nty * ntz * ntt;
   a.ngroups = 1;
-  const int nc = stream_block(a.g, a.sy, a.sz);
+  const int nc = stream_block(a.g, a.sy, a.sz, PI);
   const dim3 grid(a.ntiles * a.nrhs);
   if constexpr (PI != DIRAC_F64) {
-    if (nc == 512) {
-      hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 512>), grid, dim3(512),
-                         (stream_lds_bytes<PI, 512>()), st, a);
+    if (nc != 128 && nc != 256) {
+      if (nc == 192)
+        hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 192>), grid, dim3(192),
+                           (stream_lds_bytes<PI, 192>()), st, a);
+      else if (nc == 384)
+        hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 384>), grid, dim3(384),
+                           (stream_lds_bytes<PI, 384>()), st, a);
+      else
+        hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 512>), grid, dim3(512),
+                           (stream_lds_bytes<PI, 512>()), st, a);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess || EPI == kEpiStore) return e;
       return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);

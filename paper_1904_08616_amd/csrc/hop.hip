@@ -79,7 +79,7 @@ k_hop(DslashArgs a) {
         // stencil (the two differ for the scaled 16-bit formats)
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) s += (double)o[k].re * q[k].re + (double)o[k].im * q[k].im;
+        for (int k = 0; k < 12; ++k) s = fma((double)o[k].im, (double)q[k].im, fma((double)o[k].re, (double)q[k].re, s));
         vals[0][0] = s;
       }
     } else {
@@ -91,7 +91,7 @@ k_hop(DslashArgs a) {
       for (int k = 0; k < 12; ++k) {
         d[k].re = fma(-cf, o[k].re, d[k].re);
         d[k].im = fma(-cf, o[k].im, d[k].im);
-        s += (double)d[k].re * d[k].re + (double)d[k].im * d[k].im;
+        s = fma((double)d[k].im, (double)d[k].im, fma((double)d[k].re, (double)d[k].re, s));
       }
       SO::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, d);
       vals[0][0] = s;

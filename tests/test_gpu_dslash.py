@@ -276,9 +276,11 @@ def test_split_kernel_parity(prec, link, tol, dagger):
 
 STREAM_CASES = [
     # dims, (tile_y, tile_z), t_chunk    (tile = all of x times tile_y times tile_z: 32 to 512
-    # columns in a block of 128, 256 or 512 threads; spare threads idle)
+    # columns in a block of 128, 192, 256, 384 or 512 threads, float64 128 or 256; spare
+    # threads idle)
     ((12, 6, 4, 6), (2, 2), 2),    # 48 of 128 threads
-    ((24, 4, 6, 4), (2, 3), 3),    # 144 of 256 threads, ragged chunk
+    ((24, 4, 6, 4), (2, 3), 3),    # 144 of 192 threads (float64 256), ragged chunk
+    ((24, 4, 8, 4), (2, 4), 2),    # 192 of 192 threads (float64 256)
     ((6, 4, 4, 4), (4, 4), 1),     # 96 columns, one tile spans y and z
     ((2, 4, 4, 4), (4, 4), 2),     # X = 2: both x hops reach the same neighbour
     ((8, 4, 4, 8), (4, 4), 1),
@@ -291,7 +293,8 @@ STREAM_CASES = [
     # 512 threads (32- and 16-bit formats)
     ((32, 4, 4, 6), (4, 4), 4),    # 512 columns, ragged last chunk
     ((16, 8, 8, 6), (8, 4), 2),    # faces in z only
-    ((24, 4, 6, 4), (2, 6), 3),    # 288 of 512 threads
+    ((24, 4, 6, 4), (2, 6), 3),    # 288 of 384 threads
+    ((24, 4, 8, 4), (4, 4), 2),    # 384 of 384 threads
     ((16, 8, 8, 4), (4, 8), 4),    # one chunk covers all of t
 ]
 
