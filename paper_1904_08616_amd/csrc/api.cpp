@@ -228,8 +228,9 @@ bool parse_key(const char* key, Geom* g, int* nrhs, int* prec) {
   return true;
 }
 
-// Every line is checked like dirac_set_launch_config's argument; lines of
-// another format version, or that do not fit their geometry, are skipped.
+// Every line is checked like dirac_set_launch_config's argument; lines that
+// do not parse, of another format version, or that do not fit their geometry
+// are skipped.
 void load_cache_file_locked() {
   if (g_cfg_loaded) return;
   g_cfg_loaded = true;
@@ -237,10 +238,12 @@ void load_cache_file_locked() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  char key[256];
-  LaunchCfg c;
-  while (std::fscanf(f, "%255s %d %d %d %d %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds, &c.nt, &c.sy, &c.sz,
-                     &c.tc) == 9) {
+  char line[512], key[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    LaunchCfg c;
+    if (std::sscanf(line, "%255s %d %d %d %d %d %d %d %d", key, &c.S, &c.R, &c.remap, &c.lds, &c.nt, &c.sy, &c.sz,
+                    &c.tc) != 9)
+      continue;
     Geom g;
     int nrhs = 0, prec = 0;
     if (!parse_key(key, &g, &nrhs, &prec) || check_cfg(g, nrhs, prec, c) != nullptr) continue;

@@ -269,6 +269,7 @@ def test_tune_cache_entries_are_validated(tmp_path):
     import sys
     cache = tmp_path / "tune.txt"
     cache.write_text(
+        "a line that does not parse\n"                            # skipped, the rest still read
         "v2|unknown|4x4x4x4|p0|l18|n1 128 2 1 0 1 1 1 1\n"       # valid per-site entry
         "v2|unknown|8x4x4x4|p0|l18|n1 96 1 1 0 0 1 1 1\n"        # block of 96 sites
         "v2|unknown|16x16x16x16|p0|l18|n1 64 1 7 1 0 8 8 2\n"    # tile of 1024 columns
