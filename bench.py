@@ -436,28 +436,39 @@ def bench_multi_lattice(torch, D, steps):
         "separate_ms": round(sep, 4), "separate_GB/s": round(total / (sep * 1e-3) / 1e9, 1)}}
 
 
-def bench_force(torch, D, steps):
-    """Link force (the backward of D with respect to U) and one autograd
-    forward + backward of chi = D(U) psi on 16^4 in float64."""
+def time_force(torch, D, dims, steps, seed=0):
+    """Average ms of one link-force launch (float64) on ``dims`` and its
+    algorithmic bytes: g and psi read once, 4 complex128 3x3 matrices
+    written per site."""
     import synth
-    dims = (16, 16, 16, 16)
-    V = int(np.prod(dims))
-    g = synth.rng(0)
-    U = synth.links_exp(dims, 0.3, g)
+    g = synth.rng(seed)
     psi = synth.spinor_gauss(dims, g)
     gchi = synth.spinor_gauss(dims, g)
     op = D.Operator(dims, 0.1, "f64", 18)
     pi = op.pack_spinor(torch.from_numpy(psi).cuda())
     gi = op.pack_spinor(torch.from_numpy(gchi).cuda())
+    del psi, gchi
     F = torch.zeros(op.gauge_shape(), dtype=torch.complex128, device="cuda")
     for _ in range(5):
         op.force(gi, pi, out=F)
-    reps = max(50, steps // 2)
     with Timer(torch) as t:
-        for _ in range(reps):
+        for _ in range(steps):
             op.force(gi, pi, out=F)
-    ms = t.ms / reps
-    fb = V * (2 * 192 + 4 * 9 * 16)  # g and psi read once, 4 complex128 3x3 written
+    return t.ms / steps, int(np.prod(dims)) * (2 * 192 + 4 * 9 * 16)
+
+
+def bench_force(torch, D, steps):
+    """Link force (the backward of D with respect to U) on 16^4 and on
+    32^3 x 64 (2.0 GB per launch, beyond the last-level cache) in float64, and
+    one autograd forward + backward of chi = D(U) psi on 16^4."""
+    import synth
+    dims = (16, 16, 16, 16)
+    g = synth.rng(0)
+    U = synth.links_exp(dims, 0.3, g)
+    psi = synth.spinor_gauss(dims, g)
+    gchi = synth.spinor_gauss(dims, g)
+    ms, fb = time_force(torch, D, dims, max(50, steps // 2))
+    ms_big, fb_big = time_force(torch, D, (32, 32, 32, 64), max(20, steps // 8))
     Ut = torch.from_numpy(U).cuda().requires_grad_(True)
     pt = torch.from_numpy(psi).cuda().requires_grad_(True)
     gt = torch.from_numpy(gchi).cuda()
@@ -468,6 +479,8 @@ def bench_force(torch, D, steps):
             D.DiracApply.apply(Ut, pt, 0.1).backward(gt)
     return {"force_16x16x16x16_f64": {"ms": round(ms, 4), "GB/s": round(fb / (ms * 1e-3) / 1e9, 1),
                                       "frac": round(fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "force_32x32x32x64_f64": {"ms": round(ms_big, 4), "GB/s": round(fb_big / (ms_big * 1e-3) / 1e9, 1),
+                                      "frac": round(fb_big / (ms_big * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "autograd_dirac_apply_16x16x16x16_f64_fwd_bwd_ms": round(t.ms / 10, 3)}
 
 
@@ -655,6 +668,11 @@ def main(argv=None):
     ap.add_argument("--profile-eo", action="store_true",
                     help="only the even-odd Schur operator and the 32^3x64 solves of D x = b (float64 and F16S "
                          "inner), one JSON line; for kernel traces of the half-lattice hops")
+    ap.add_argument("--profile-dslash", default=None, metavar="PREC/LINK",
+                    help="only the D of this format on 32^3x64 (e.g. f64/12) in the --headline-launch configuration "
+                         "(else tuned), after a --copy-gib copy that calibrates the byte counters; for counter runs")
+    ap.add_argument("--profile-force", action="store_true",
+                    help="only the float64 link force on 16^4 and 32^3x64, one JSON line; for kernel traces")
     ap.add_argument("--profile-mrhs", default=None, metavar="LAUNCH",
                     help="only the 12-source float32 Dslash on 24^3x48 in this JSON launch configuration (no "
                          "tuning), after a 1 GiB copy that calibrates the byte counters; for counter runs")
@@ -674,6 +692,26 @@ def main(argv=None):
         Ub, pb = gen_inputs(big, seed=0)
         res = {inner: cg_time(torch, D, big, Ub, pb, 0.02, inner, link=12) for inner in ("f64", "f32", "f16s")}
         print(json.dumps({"cg_32x32x32x64_m0.02_link12": res}), flush=True)
+        return 0
+    if a.profile_force:
+        res = {}
+        for dims in ((16, 16, 16, 16), (32, 32, 32, 64)):
+            ms, fb = time_force(torch, D, dims, a.steps)
+            res["force_%dx%dx%dx%d_f64" % dims] = {"ms": round(ms, 4), "GB/s": round(fb / (ms * 1e-3) / 1e9, 1)}
+        print(json.dumps(res), flush=True)
+        return 0
+    if a.profile_dslash:
+        prec, link = a.profile_dslash.split("/")
+        copy_ceiling(torch, D, a.copy_gib)
+        dims = HEADLINE_DIMS
+        log("generating 32^3x64 inputs")
+        Ub, pb = gen_inputs(dims, seed=0)
+        launch = json.loads(a.headline_launch) if a.headline_launch else None
+        ms, _, cfg = time_dslash(torch, D, dims, prec, int(link), Ub, pb, a.steps, a.warmup, m_q=HEADLINE_MQ,
+                                 launch=launch)
+        by = site_bytes(prec, int(link)) * int(np.prod(dims))
+        print(json.dumps({f"dslash_32x32x32x64_{prec}_link{link}": {
+            "ms": round(ms, 4), "GB/s": round(by / (ms * 1e-3) / 1e9, 1), "launch": cfg}}), flush=True)
         return 0
     if a.profile_mrhs:
         print(json.dumps({"dslash_24x24x24x48_f32_link12_12rhs": profile_multi_rhs(torch, D, a.profile_mrhs,
