@@ -351,7 +351,8 @@ int dirac_plan_destroy(void* plan);
  *     combined in LDS (nrhs = 1; for lattices too small to fill the device);
  *   - t-streaming (lds = 1): a block owns all of x times tile_y rows times
  *     tile_z planes (32 to 512 columns, float64 up to 256, in a block of
- *     128, 256 or 512 threads) and walks t_chunk time slices; the current
+ *     128, 192, 256, 384 or 512 threads, float64 128 or 256) and walks
+ *     t_chunk time slices; the current
  *     slice is staged in LDS and the t neighbours stay in registers
  *     (tile_y | Ly and tile_z | Lz; one block per tile and right-hand side,
  *     the blocks of a tile adjacent so that they share its links in the L2).
