@@ -5,6 +5,8 @@ float32 <= 5e-6 against the oracle on the same (rounded) inputs; scaled
 float16 / bfloat16 against the oracle on the rounded inputs, to the output
 rounding of the format."""
 
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -220,13 +222,20 @@ def test_full_size_32x32x32x8_f64():
         assert rel_inf(got, ref) <= 1e-13, op.launch_config()
 
 
+@functools.lru_cache(maxsize=1)
+def _inputs_32x32x32x64():
+    # the benchmark's 32^3 x 64 inputs (generating them takes about a minute),
+    # shared by the full-size tests of this module
+    return inputs((32, 32, 32, 64), "exp", seed=0)
+
+
 def test_full_size_32x32x32x64_sampled():
     # configuration: 32^3 x 64, exp(i 0.3 H) links, m = 0.02; float64 on a
     # sample of sites (and every corner), float32 / float16s likewise.
     # Each precision in its default launch and in the autotuner's pick (the
     # launch the benchmark times).
     dims = (32, 32, 32, 64)
-    U, psi = inputs(dims, "exp", seed=0)
+    U, psi = _inputs_32x32x32x64()
     m = 0.02
     sites = sample_sites(dims, 2000)
     ref = wilson.dslash_at(U, psi, m, sites)
@@ -247,6 +256,37 @@ def test_full_size_32x32x32x64_sampled():
             del out
         del Ui, pi
         torch.cuda.empty_cache()
+
+
+def test_full_size_32x32x32x64_every_site_in_the_headline_launch():
+    # the benchmark's headline as it is timed: float64 18-real D on 32^3 x 64
+    # in the launch of the committed counter record (and in the autotuner's
+    # pick), every site against the oracle's full operator
+    import json
+
+    import bench
+    dims = bench.HEADLINE_DIMS
+    assert dims == (32, 32, 32, 64)
+    U, psi = _inputs_32x32x32x64()
+    m = bench.HEADLINE_MQ
+    ref = wilson.dslash(U, psi, m)
+    with open(bench.TRAFFIC_RECORD) as f:
+        launch = json.load(f)["launch"]
+    op = D.Operator(dims, m, "f64", 18)
+    Ui, pi = op.pack_gauge(cuda(U)), op.pack_spinor(cuda(psi))
+    del U, psi
+    for tuned in (False, True):
+        if tuned:
+            op.autotune(Ui, pi, op.empty_spinor())
+        else:
+            op.set_launch_config(**{k: v for k, v in launch.items() if k != "tuned"})
+        out = host(op.unpack_spinor(op.apply(Ui, pi)))
+        err = rel_inf(out, ref)
+        print(f"32^3x64 f64/18 every site, {op.launch_config()}: err {err:.2e}")
+        assert err <= 1e-13
+        del out
+    del Ui, pi
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 12, 5e-6),
