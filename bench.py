@@ -661,7 +661,8 @@ def main(argv=None):
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the plain copy measured as the bandwidth ceiling (0: skip)")
     ap.add_argument("--headline-launch", default=None,
-                    help="JSON launch configuration of the headline Dslash (no tuning); for profiling runs")
+                    help="JSON launch configuration of the headline Dslash, or of the --profile-dslash one (no "
+                         "tuning); for profiling runs")
     ap.add_argument("--profile-cg", action="store_true",
                     help="only the 32^3x64 CG solves (float64, F32 and F16S inner), one JSON line; "
                          "for kernel traces of the solver (run after a full bench with DIRAC_TUNE_CACHE set)")
