@@ -193,6 +193,37 @@ def tune_for_solve(op, U_int, src_int):
         op.autotune(U_int, src_int, op.empty_spinor())
 
 
+def cg_iteration_bytes(prec, link):
+    """Compulsory bytes per site of one CG iteration as the library runs it:
+    D p with |Dp|^2 (links, p, t), D^dag t with r -= alpha D^dag t and |r|^2
+    (links, t, r read and written), and x += alpha p, p = r + beta p (x and p
+    read and written, r read): two link passes, five spinor passes in the
+    iteration's format (p, t) and five in the vectors' (x, r; float32 for a
+    low-precision inner solve)."""
+    link_b = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}[prec] * link * 4
+    spin = {"f64": 192, "f32": 96, "f16s": 52, "bf16s": 52}[prec]
+    vec = 192 if prec == "f64" else 96
+    return 2 * link_b + 5 * spin + 5 * vec
+
+
+def cg_bound(dims, r, inner, link):
+    """HBM lower bound of a solve from its counted applications: every inner
+    iteration at cg_iteration_bytes of its format, every other pair of
+    float64 applications (true residuals, restarts) at its two link passes and
+    five float64 spinor passes."""
+    V = int(np.prod(dims))
+    if inner == "f64":
+        it = r["iters"]
+        pairs = max(0, r["dslash_hi"] // 2 - it)
+        by = it * cg_iteration_bytes("f64", link) + pairs * (2 * 8 * link * 4 + 5 * 192)
+    else:
+        lo_link = link if inner == "f32" else 12
+        it = r["dslash_lo"] // 2
+        by = it * cg_iteration_bytes(inner, lo_link) + (r["dslash_hi"] // 2) * (2 * 8 * link * 4 + 5 * 192)
+    ms = by * V / (HBM_PEAK_GBS * 1e9) * 1e3
+    return round(ms, 2), round(ms / r["ms"], 3)
+
+
 def cg_time(torch, D, dims, U, eta, m_q, inner, link=18, tol=1e-10, reps=1):
     op = D.Operator(dims, m_q, "f64", link)
     Ui = op.pack_gauge(torch.from_numpy(U).cuda())
@@ -214,6 +245,7 @@ def cg_time(torch, D, dims, U, eta, m_q, inner, link=18, tol=1e-10, reps=1):
                  status=st[0]["status"], dslash_hi=st[0]["dslash_hi"], dslash_lo=st[0]["dslash_lo"])
         if best is None or r["ms"] < best["ms"]:
             best = r
+    best["hbm_bound_ms"], best["frac_of_bound"] = cg_bound(dims, best, inner, link)
     return best
 
 

@@ -44,3 +44,15 @@ def test_committed_record_names_the_headline_kernel():
     name = bench.kernel_name("f64", 18, rec["launch"], bench.HEADLINE_DIMS).split(" (")[0]
     assert name in rec["FETCH_SIZE"]["kernel"] and name in rec["WRITE_SIZE"]["kernel"]
     assert rec["traffic_bytes"] > bench.site_bytes("f64", 18) * 32 ** 3 * 64
+
+
+def test_cg_bound_counts_the_library_iteration():
+    # two link passes, five spinor passes of the iteration's format and five
+    # of the solution/residual vectors (float32 below float64)
+    assert bench.cg_iteration_bytes("f64", 12) == 2 * 384 + 10 * 192
+    assert bench.cg_iteration_bytes("f64", 18) == 2 * 576 + 10 * 192
+    assert bench.cg_iteration_bytes("f32", 12) == 2 * 192 + 10 * 96
+    assert bench.cg_iteration_bytes("f16s", 12) == 2 * 96 + 5 * 52 + 5 * 96
+    V = 32 ** 3 * 64
+    ms, frac = bench.cg_bound((32, 32, 32, 64), dict(ms=400.0, iters=300, dslash_hi=604, dslash_lo=0), "f64", 12)
+    assert abs(ms - (300 * 2688 + 2 * 1728) * V / 8e12 * 1e3) < 0.01 and abs(frac - ms / 400.0) < 1e-3
