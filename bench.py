@@ -704,6 +704,8 @@ def main(argv=None):
     ap.add_argument("--profile-dslash", default=None, metavar="PREC/LINK",
                     help="only the D of this format on 32^3x64 (e.g. f64/12) in the --headline-launch configuration "
                          "(else tuned), after a --copy-gib copy that calibrates the byte counters; for counter runs")
+    ap.add_argument("--profile-dims", default="32x32x32x64", metavar="XxYxZxT",
+                    help="lattice of --profile-dslash (default the headline's)")
     ap.add_argument("--profile-force", action="store_true",
                     help="only the float64 link force on 16^4 and 32^3x64, one JSON line; for kernel traces")
     ap.add_argument("--profile-mrhs", default=None, metavar="LAUNCH",
@@ -736,14 +738,15 @@ def main(argv=None):
     if a.profile_dslash:
         prec, link = a.profile_dslash.split("/")
         copy_ceiling(torch, D, a.copy_gib)
-        dims = HEADLINE_DIMS
-        log("generating 32^3x64 inputs")
+        dims = tuple(int(v) for v in a.profile_dims.split("x"))
+        log(f"generating {a.profile_dims} inputs")
         Ub, pb = gen_inputs(dims, seed=0)
         launch = json.loads(a.headline_launch) if a.headline_launch else None
-        ms, _, cfg = time_dslash(torch, D, dims, prec, int(link), Ub, pb, a.steps, a.warmup, m_q=HEADLINE_MQ,
+        m_q = HEADLINE_MQ if dims == HEADLINE_DIMS else 0.05
+        ms, _, cfg = time_dslash(torch, D, dims, prec, int(link), Ub, pb, a.steps, a.warmup, m_q=m_q,
                                  launch=launch)
         by = site_bytes(prec, int(link)) * int(np.prod(dims))
-        print(json.dumps({f"dslash_32x32x32x64_{prec}_link{link}": {
+        print(json.dumps({f"dslash_{a.profile_dims}_{prec}_link{link}": {
             "ms": round(ms, 4), "GB/s": round(by / (ms * 1e-3) / 1e9, 1), "launch": cfg}}), flush=True)
         return 0
     if a.profile_mrhs:
