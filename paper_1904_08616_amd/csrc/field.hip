@@ -286,10 +286,12 @@ __global__ void __launch_bounds__(kBlock) k_axpby(Geom g, int nb, FieldDev x, Fi
   SpinFmt<PY>::store(field_rsrc(y, s.rhs), g.Vh, s.p, s.i, yv);
 }
 
-// x += alpha p; p = r + beta p   (where the right-hand side is active)
+// x += alpha p; p = r + beta p   (where the right-hand side is active).  In
+// float64 the three fields' 36 loads take 144 registers: the register budget
+// of three waves per SIMD lets every load be in flight before the first wait.
 template <int PX, int PP, int PR>
-__global__ void __launch_bounds__(kBlock) k_cg_xp(Geom g, int nb, FieldDev x, FieldDev p, FieldDev r,
-                                                  const CgState* st) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PX == DIRAC_F64 ? 3 : 4)))
+k_cg_xp(Geom g, int nb, FieldDev x, FieldDev p, FieldDev r, const CgState* st) {
   SiteIdx s = site_idx(g, nb);
   if (!s.valid) return;
   const CgState& S = st[s.rhs];
@@ -303,6 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_xp(Geom g, int nb, FieldDev x, Fi
   SpinFmt<PX>::load(xr, g.Vh, s.p, s.i, xv);
   SpinFmt<PP>::load(pr, g.Vh, s.p, s.i, pv);
   SpinFmt<PR>::load(field_rsrc(r, s.rhs), g.Vh, s.p, s.i, rv);
+  __builtin_amdgcn_sched_barrier(0);  // every load issued before the first use
   const RX alpha = (RX)S.alpha;
   const RP beta = (RP)S.beta;
 #pragma unroll
