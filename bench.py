@@ -55,7 +55,8 @@ def kernel_name(prec, link, cfg, dims, dagger=False):
     """Which Dslash kernel a launch configuration selects, as rocprofv3 names it
     (template arguments: input/output precision, link reals, dagger, epilogue,
     then rhs per thread, waves per site, or threads per block and whether
-    the walk requests loads one direction ahead)."""
+    the walk requests loads one direction ahead and face spinors one slice
+    ahead)."""
     P = {"f64": 0, "f32": 1, "f16s": 2, "bf16s": 3}[prec]
     args = f"{P}, {P}, {link}, {'true' if dagger else 'false'}, 0"
     if cfg["lds"]:
@@ -65,7 +66,8 @@ def kernel_name(prec, link, cfg, dims, dagger=False):
         else:
             nc = next((b for b in (128, 192, 256, 384) if cols <= b), 512)
         pipe = "true" if prec == "f64" and cfg["xcd_remap"] & 8 else "false"
-        return (f"k_dslash_stream<{args}, {nc}, {pipe}> (tile all-x * {cfg['tile_y']} * {cfg['tile_z']}, "
+        ahead = "true" if prec == "f64" and cfg["xcd_remap"] & 16 else "false"
+        return (f"k_dslash_stream<{args}, {nc}, {pipe}, {ahead}> (tile all-x * {cfg['tile_y']} * {cfg['tile_z']}, "
                 f"t_chunk {cfg['t_chunk']})")
     if cfg["rhs_per_thread"] < 0:
         return f"k_dslash_split<{args}, {-cfg['rhs_per_thread']}> ({cfg['block_sites']} sites/block)"
@@ -78,11 +80,13 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dslash_f64_32x32x32x64_traffic.
 
 # Streaming launches of the headline timed beside the autotuner's pick
 # (tile_y x tile_z, t_chunk, launch-order flags; flag 8: loads one direction
-# ahead), the fastest in sweeps on 32^3 x 64.
+# ahead, flag 16: face spinors one slice ahead), the fastest in sweeps on
+# 32^3 x 64.
 HEADLINE_CANDIDATES = [
     dict(block_sites=64, rhs_per_thread=1, xcd_remap=r, nt_store=1, lds=1, tile_y=ty, tile_z=tz, t_chunk=tc)
     for (ty, tz, tc, r) in ((4, 2, 32, 1), (4, 2, 32, 9), (4, 2, 16, 4), (4, 2, 16, 12), (4, 2, 32, 3),
-                            (4, 1, 32, 9), (8, 1, 32, 9))
+                            (4, 1, 32, 9), (8, 1, 32, 9), (4, 2, 32, 17), (4, 2, 32, 25), (4, 2, 16, 20),
+                            (4, 2, 16, 28), (2, 4, 32, 25), (2, 4, 32, 17))
 ]
 
 

@@ -361,7 +361,11 @@ int dirac_plan_destroy(void* plan);
  * bit 1 t-chunks fastest in the block order, bit 2 odd t-chunks walk down in
  * t, so that neighbouring chunks read their shared halo slice at the same
  * time; bit 3 (float64 only) requests each direction's links and spinors one
- * direction ahead of its hops, so that two directions' loads are in flight.
+ * direction ahead of its hops, so that two directions' loads are in flight;
+ * bit 4 (float64 only; tile_y and tile_z at least 2, else DIRAC_EINVAL)
+ * loads the spinors beyond the tile's y and z faces one time slice ahead,
+ * in the step in which the neighbouring tile reads them, so that the L2
+ * serves the second read.
  * nt_store writes the output with non-temporal stores. */
 typedef struct dirac_launch {
   int32_t block_sites;

@@ -188,11 +188,13 @@ std::string cfg_key(const OpInfo& o) {
 // (nullptr) or why not; normalises the fields the chosen kernel ignores.
 const char* check_cfg(const Geom& g, int nrhs, int prec, LaunchCfg& c) {
   if (c.lds) {
-    if (c.remap < 0 || c.remap > (prec == DIRAC_F64 ? 15 : 7))
-      return "xcd_remap of the streaming kernel is a 3-bit mask (float64: 4 bits)";
+    if (c.remap < 0 || c.remap > (prec == DIRAC_F64 ? 31 : 7))
+      return "xcd_remap of the streaming kernel is a 3-bit mask (float64: 5 bits)";
     if (!stream_fits(g, c.sy, c.sz, c.tc, prec))
       return "the streaming tile must divide the lattice and have 32 to 512 columns (float64: 256), "
              "t_chunk >= 1";
+    if ((c.remap & kStreamAhead) && !stream_ahead_fits(c.sy, c.sz))
+      return "xcd_remap bit 4 (face spinors one slice ahead) needs tile_y >= 2 and tile_z >= 2";
     c.S = 64;
     c.R = 1;
     c.lds = 1;
@@ -824,10 +826,12 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
           if (R < 0 && S != 64) continue;  // the split kernel has fixed 64-site blocks
           cands.push_back(LaunchCfg{S, R, remap, 0, nt, 1, 1, 1, 1});
         }
-  // streaming kernel: XCD order, t-chunks fastest, alternating walk (bits 0..2)
+  // streaming kernel: XCD order, t-chunks fastest, alternating walk (bits
+  // 0..2); float64 also the pipelined walk and faces one slice ahead
   for (const LaunchCfg& c0 : stream_candidates(o))
-    for (int remap = 0; remap < (o.prec == DIRAC_F64 ? 16 : 8); ++remap)
+    for (int remap = 0; remap < (o.prec == DIRAC_F64 ? 32 : 8); ++remap)
       for (int nt : {0, 1}) {
+        if ((remap & kStreamAhead) && !stream_ahead_fits(c0.sy, c0.sz)) continue;
         LaunchCfg c = c0;
         c.remap = remap;
         c.nt = nt;

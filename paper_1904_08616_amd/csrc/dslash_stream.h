@@ -93,6 +93,7 @@ constexpr int kStreamXcd = 1;   // XCD-contiguous block order
 constexpr int kStreamTFast = 2; // t-chunks fastest in the block order
 constexpr int kStreamAlt = 4;   // odd t-chunks walk downwards
 constexpr int kStreamPipe = 8;  // float64: loads one direction ahead (stream_walk's PIPE)
+constexpr int kStreamAhead = 16; // float64: face spinors loaded one slice ahead (stream_walk's AHEAD)
 
 // Store the output o of site (p, i) of right-hand side rhs, with the
 // epilogue EPI: plain store, store and |o|^2 (of the value as stored), or
@@ -141,7 +142,15 @@ __device__ __forceinline__ void stream_epilogue(const DslashArgs& a, int rhs, in
 // U (1 - S gamma_t) psi(n) carried into n - t.  Neighbouring chunks that walk
 // in opposite directions read their shared halo slice and link at the same
 // time (both at the start, or both at the end of the walk).
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN>
+//
+// AHEAD: a thread's y and z neighbours outside the tile (at most one of each
+// when tile_y and tile_z are at least 2) are requested one slice ahead, at
+// the start of the step, next to psi(tn), and carried in registers into the
+// next step.  The neighbouring tile requests the same spinors as its own
+// psi(tn) at the start of that step, so the second request finds them in the
+// L2; requested in the step that uses them they come a whole step (more than
+// an XCD's L2 of traffic) after the first.
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN, bool AHEAD = false>
 __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool act, int x, int y, int z, int yl,
                                             int zl, int t0, int t1, char* lds_raw, double& val) {
   using SI = SpinFmt<PI>;
@@ -172,6 +181,10 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
   const int ccol_yp = ccol + (yp - y) * g.X, ccol_ym = ccol + (ym - y) * g.X;
   const int ccol_zp = ccol + (zp - z) * g.X * g.Y, ccol_zm = ccol + (zm - z) * g.X * g.Y;
   const int slice = g.X * g.Y * g.Z;
+  // AHEAD: the one y and one z neighbour column outside the tile, if any
+  const int ccol_fy = in_yp ? ccol_ym : ccol_yp, ccol_fz = in_zp ? ccol_zm : ccol_zp;
+  const bool has_fy = !(in_yp && in_ym), has_fz = !(in_zp && in_zm);
+  Cx<Rl> fy[12], fz[12];
   auto at = [&](int col, int par, int t, int& p, int& i) {
     p = (par + t) & 1;
     i = (t * slice + col) >> 1;
@@ -211,6 +224,17 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
 #pragma unroll
       for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
     }
+    if constexpr (AHEAD) {
+      int pf, jf;
+      if (has_fy) {
+        at(ccol_fy, cpar ^ 1, ts, pf, jf);
+        SI::load(in, Vh, pf, jf, fy);
+      }
+      if (has_fz) {
+        at(ccol_fz, cpar ^ 1, ts, pf, jf);
+        SI::load(in, Vh, pf, jf, fz);
+      }
+    }
   }
   __syncthreads();
 
@@ -228,6 +252,20 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
     at(ccol, cpar, tn, pn, in_);
     Cx<Rl> nxt[12];
     SI::load(in, Vh, pn, in_, nxt);
+    Cx<Rl> fyn[12], fzn[12];  // AHEAD: the faces of slice tn
+    if constexpr (AHEAD) {
+      if (s + 1 < nsteps) {
+        int pf, jf;
+        if (has_fy) {
+          at(ccol_fy, cpar ^ 1, tn, pf, jf);
+          SI::load(in, Vh, pf, jf, fyn);
+        }
+        if (has_fz) {
+          at(ccol_fz, cpar ^ 1, tn, pf, jf);
+          SI::load(in, Vh, pf, jf, fzn);
+        }
+      }
+    }
 
     Cx<Rl> acc[12];
 #pragma unroll
@@ -257,6 +295,9 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       LF::load(Ur, Vh, p, 1, i, u);
       if (in_yp) {
         cur_s.get(tid + g.X, v);
+      } else if constexpr (AHEAD) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = fy[k];
       } else {
         int pf, jf;
         at(ccol_yp, cpar ^ 1, t, pf, jf);
@@ -267,10 +308,14 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         int pb, ib;
         at(ccol_ym, cpar ^ 1, t, pb, ib);
         LF::load(Ur, Vh, pb, 1, ib, u);
-        if (in_ym)
+        if (in_ym) {
           cur_s.get(tid - g.X, v);
-        else
+        } else if constexpr (AHEAD) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) v[k] = fy[k];
+        } else {
           SI::load(in, Vh, pb, ib, v);
+        }
       }
       hop_apply<1, DAG, false, SI::kScaled>(u, v, acc);
       pin12(acc);
@@ -278,6 +323,9 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       LF::load(Ur, Vh, p, 2, i, u);
       if (in_zp) {
         cur_s.get(tid + g.X * BY, v);
+      } else if constexpr (AHEAD) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = fz[k];
       } else {
         int pf, jf;
         at(ccol_zp, cpar ^ 1, t, pf, jf);
@@ -288,10 +336,14 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
         int pb, ib;
         at(ccol_zm, cpar ^ 1, t, pb, ib);
         LF::load(Ur, Vh, pb, 2, ib, u);
-        if (in_zm)
+        if (in_zm) {
           cur_s.get(tid - g.X * BY, v);
-        else
+        } else if constexpr (AHEAD) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) v[k] = fz[k];
+        } else {
           SI::load(in, Vh, pb, ib, v);
+        }
       }
       hop_apply<2, DAG, false, SI::kScaled>(u, v, acc);
       pin12(acc);
@@ -315,6 +367,13 @@ __device__ __forceinline__ void stream_walk(const DslashArgs& a, int rhs, bool a
       }
     }
 
+    if constexpr (AHEAD) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        fy[k] = fyn[k];
+        fz[k] = fzn[k];
+      }
+    }
     // epilogue at site (p, i) with centre psi(t)
     Cx<Rl> cur[12];
     cur_s.get(tid, cur);
@@ -344,8 +403,9 @@ struct DirLoads {
 // directions' loads are in flight while the wave computes, instead of one
 // round trip to memory per direction.  It needs about twice the registers
 // (float64: VGPRs and AGPRs of a wave running alone on its SIMD, which the
-// LDS of a float64 walk imposes anyway).
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN>
+// LDS of a float64 walk imposes anyway).  AHEAD as in stream_walk: the face
+// spinors then come one slice ahead and a direction's requests are its links.
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool DOWN, bool AHEAD = false>
 __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, bool act, int x, int y, int z, int yl,
                                             int zl, int t0, int t1, char* lds_raw, double& val) {
   using SI = SpinFmt<PI>;
@@ -376,6 +436,9 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
   const int ccol_yp = ccol + (yp - y) * g.X, ccol_ym = ccol + (ym - y) * g.X;
   const int ccol_zp = ccol + (zp - z) * g.X * g.Y, ccol_zm = ccol + (zm - z) * g.X * g.Y;
   const int slice = g.X * g.Y * g.Z;
+  const int ccol_fy = in_yp ? ccol_ym : ccol_yp, ccol_fz = in_zp ? ccol_zm : ccol_zp;
+  const bool has_fy = !(in_yp && in_ym), has_fz = !(in_zp && in_zm);
+  Cx<Rl> fy[12], fz[12];
   auto at = [&](int col, int par, int t, int& p, int& i) {
     p = (par + t) & 1;
     i = (t * slice + col) >> 1;
@@ -415,6 +478,17 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
 #pragma unroll
       for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
     }
+    if constexpr (AHEAD) {
+      int pf, jf;
+      if (has_fy) {
+        at(ccol_fy, cpar ^ 1, ts, pf, jf);
+        SI::load(in, Vh, pf, jf, fy);
+      }
+      if (has_fz) {
+        at(ccol_fz, cpar ^ 1, ts, pf, jf);
+        SI::load(in, Vh, pf, jf, fz);
+      }
+    }
   }
   __syncthreads();
 
@@ -442,14 +516,18 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
     auto req_y = [&](DirLoads<PI, LK>& d) {
       LF::load(Ur, Vh, p, 1, i, d.uf);
       LF::load(Ur, Vh, pyb, 1, iyb, d.ub);
-      if (!in_yp) SI::load(in, Vh, pyf, iyf, d.vf);
-      if (!in_ym) SI::load(in, Vh, pyb, iyb, d.vb);
+      if constexpr (!AHEAD) {
+        if (!in_yp) SI::load(in, Vh, pyf, iyf, d.vf);
+        if (!in_ym) SI::load(in, Vh, pyb, iyb, d.vb);
+      }
     };
     auto req_z = [&](DirLoads<PI, LK>& d) {
       LF::load(Ur, Vh, p, 2, i, d.uf);
       LF::load(Ur, Vh, pzb, 2, izb, d.ub);
-      if (!in_zp) SI::load(in, Vh, pzf, izf, d.vf);
-      if (!in_zm) SI::load(in, Vh, pzb, izb, d.vb);
+      if constexpr (!AHEAD) {
+        if (!in_zp) SI::load(in, Vh, pzf, izf, d.vf);
+        if (!in_zm) SI::load(in, Vh, pzb, izb, d.vb);
+      }
     };
     auto req_t = [&](M3<Rl>& u) {  // U_t(n - t) walking down, U_t(n) walking up
       if constexpr (DOWN)
@@ -460,6 +538,20 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
     // psi(tn) and the x links first
     Cx<Rl> nxt[12];
     SI::load(in, Vh, pn, in_, nxt);
+    Cx<Rl> fyn[12], fzn[12];  // AHEAD: the faces of slice tn
+    if constexpr (AHEAD) {
+      if (s + 1 < nsteps) {
+        int pf, jf;
+        if (has_fy) {
+          at(ccol_fy, cpar ^ 1, tn, pf, jf);
+          SI::load(in, Vh, pf, jf, fyn);
+        }
+        if (has_fz) {
+          at(ccol_fz, cpar ^ 1, tn, pf, jf);
+          SI::load(in, Vh, pf, jf, fzn);
+        }
+      }
+    }
     M3<Rl> uxf, uxb;
     LF::load(Ur, Vh, p, 0, i, uxf);
     LF::load(Ur, Vh, pxb, 0, ixb, uxb);
@@ -490,14 +582,14 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
         cur_s.get(tid + g.X, v);
       } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = dy.vf[k];
+        for (int k = 0; k < 12; ++k) v[k] = AHEAD ? fy[k] : dy.vf[k];
       }
       hop_apply<1, DAG, true, SI::kScaled>(dy.uf, v, acc);
       if (in_ym) {
         cur_s.get(tid - g.X, v);
       } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = dy.vb[k];
+        for (int k = 0; k < 12; ++k) v[k] = AHEAD ? fy[k] : dy.vb[k];
       }
       hop_apply<1, DAG, false, SI::kScaled>(dy.ub, v, acc);
       pin12(acc);
@@ -507,14 +599,14 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
         cur_s.get(tid + g.X * BY, v);
       } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = dz.vf[k];
+        for (int k = 0; k < 12; ++k) v[k] = AHEAD ? fz[k] : dz.vf[k];
       }
       hop_apply<2, DAG, true, SI::kScaled>(dz.uf, v, acc);
       if (in_zm) {
         cur_s.get(tid - g.X * BY, v);
       } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = dz.vb[k];
+        for (int k = 0; k < 12; ++k) v[k] = AHEAD ? fz[k] : dz.vb[k];
       }
       hop_apply<2, DAG, false, SI::kScaled>(dz.ub, v, acc);
       pin12(acc);
@@ -534,6 +626,13 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
       }
     }
 
+    if constexpr (AHEAD) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        fy[k] = fyn[k];
+        fz[k] = fzn[k];
+      }
+    }
     // output of site (p, i) with centre psi(t)
     Cx<Rl> cur[12];
     cur_s.get(tid, cur);
@@ -548,9 +647,9 @@ __device__ __forceinline__ void stream_walk_pipe(const DslashArgs& a, int rhs, b
   }
 }
 
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool PIPE = false>
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool PIPE = false, bool AHEAD = false>
 __global__ void __launch_bounds__(NC)
-__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? (PIPE ? 1 : 2) : DIRAC_STREAM_WAVES_F32)))
+__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? (PIPE || AHEAD ? 1 : 2) : DIRAC_STREAM_WAVES_F32)))
 k_dslash_stream(DslashArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   const Geom g = a.g;
@@ -590,14 +689,17 @@ k_dslash_stream(DslashArgs a) {
     const bool down = (a.remap & kStreamAlt) && (tt & 1);
     if constexpr (PIPE) {
       if (down)
-        stream_walk_pipe<PI, PO, LK, DAG, EPI, NC, true>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+        stream_walk_pipe<PI, PO, LK, DAG, EPI, NC, true, AHEAD>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw,
+                                                                vals[0][0]);
       else
-        stream_walk_pipe<PI, PO, LK, DAG, EPI, NC, false>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+        stream_walk_pipe<PI, PO, LK, DAG, EPI, NC, false, AHEAD>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw,
+                                                                 vals[0][0]);
     } else {
       if (down)
-        stream_walk<PI, PO, LK, DAG, EPI, NC, true>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+        stream_walk<PI, PO, LK, DAG, EPI, NC, true, AHEAD>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
       else
-        stream_walk<PI, PO, LK, DAG, EPI, NC, false>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw, vals[0][0]);
+        stream_walk<PI, PO, LK, DAG, EPI, NC, false, AHEAD>(a, rhs, act, x, y, z, yl, zl, t0, t1, lds_raw,
+                                                            vals[0][0]);
     }
   }
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, l, a.ntiles);
@@ -624,6 +726,15 @@ inline bool stream_fits(const Geom& g, int sy, int sz, int tc, int prec) {
   const int n = stream_columns(g, sy, sz);
   return n >= 32 && n <= stream_max_columns(prec);
 }
+// The walk with faces one slice ahead carries one y and one z face per
+// thread: tiles at least 2 deep in y and z.
+inline bool stream_ahead_fits(int sy, int sz) { return sy >= 2 && sz >= 2; }
+
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool PIPE, bool AHEAD>
+void launch_stream_nc(const DslashArgs& a, dim3 grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, NC, PIPE, AHEAD>), grid, dim3(NC),
+                     (stream_lds_bytes<PI, NC>()), st, a);
+}
 
 template <int PI, int PO, int LK, bool DAG, int EPI>
 hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
@@ -649,19 +760,30 @@ hipError_t launch_dslash_stream(DslashArgs a, int, hipStream_t st) {
       return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);
     }
   }
-  const bool pipe = PI == DIRAC_F64 && (a.remap & kStreamPipe);
-  if (nc == 256 && pipe)
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256, PI == DIRAC_F64>), grid, dim3(256),
-                       (stream_lds_bytes<PI, 256>()), st, a);
-  else if (nc == 256)
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 256>), grid, dim3(256),
-                       (stream_lds_bytes<PI, 256>()), st, a);
-  else if (pipe)
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128, PI == DIRAC_F64>), grid, dim3(128),
-                       (stream_lds_bytes<PI, 128>()), st, a);
-  else
-    hipLaunchKernelGGL((k_dslash_stream<PI, PO, LK, DAG, EPI, 128>), grid, dim3(128),
-                       (stream_lds_bytes<PI, 128>()), st, a);
+  // float64 walks: bit 3 pipelined, bit 4 faces one slice ahead
+  constexpr bool F = PI == DIRAC_F64;
+  const bool pipe = F && (a.remap & kStreamPipe);
+  const bool ahead = F && (a.remap & kStreamAhead);
+  if (ahead && !stream_ahead_fits(a.sy, a.sz)) return hipErrorInvalidValue;
+  if (nc == 256) {
+    if (pipe && ahead)
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 256, F, F>(a, grid, st);
+    else if (pipe)
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 256, F, false>(a, grid, st);
+    else if (ahead)
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 256, false, F>(a, grid, st);
+    else
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 256, false, false>(a, grid, st);
+  } else {
+    if (pipe && ahead)
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 128, F, F>(a, grid, st);
+    else if (pipe)
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 128, F, false>(a, grid, st);
+    else if (ahead)
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 128, false, F>(a, grid, st);
+    else
+      launch_stream_nc<PI, PO, LK, DAG, EPI, 128, false, false>(a, grid, st);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || EPI == kEpiStore) return e;
   return launch_finalize(a.red, a.ntiles, a.nrhs, 1, st);

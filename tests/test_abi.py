@@ -249,11 +249,15 @@ def test_launch_config_validation():
     got = abi.DiracLaunch()
     assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
     assert (got.lds, got.tile_y, got.tile_z, got.t_chunk, got.tuned) == (1, 4, 4, 2, 1)
-    # the streaming kernel's order flags are a 3-bit mask, 4 bits in float64
-    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 16, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
-    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 15, 0, 1, 4, 4, 2, 0))) == abi.OK
+    # the streaming kernel's order flags are a 3-bit mask, 5 bits in float64;
+    # bit 4 (face spinors one slice ahead) needs tiles at least 2 deep in y and z
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 32, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 31, 0, 1, 4, 4, 2, 0))) == abi.OK
     assert lib.dirac_launch_config(C.byref(op8), C.byref(got)) == abi.OK
-    assert got.xcd_remap == 15
+    assert got.xcd_remap == 31
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 16, 0, 1, 4, 1, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 16, 0, 1, 1, 4, 2, 0))) == abi.EINVAL
+    assert lib.dirac_set_launch_config(C.byref(op8), C.byref(L(64, 1, 15, 0, 1, 4, 1, 2, 0))) == abi.OK
     op8f = _op(dims=(8, 4, 4, 4), prec=abi.F32, link=abi.LINK12)
     assert lib.dirac_set_launch_config(C.byref(op8f), C.byref(L(64, 1, 8, 0, 1, 4, 4, 2, 0))) == abi.EINVAL
     assert lib.dirac_set_launch_config(C.byref(op8f), C.byref(L(64, 1, 7, 0, 1, 4, 4, 2, 0))) == abi.OK

@@ -9,7 +9,7 @@ from paper_1904_08616_amd import profile_summary
 
 LAUNCH = {"block_sites": 64, "rhs_per_thread": 1, "xcd_remap": 4, "nt_store": 1, "lds": 1, "tile_y": 4,
           "tile_z": 2, "t_chunk": 16, "tuned": 1}
-KERNEL = "void dirac::k_dslash_stream<0, 0, 18, false, 0, 256, false>(dirac::DslashArgs)"
+KERNEL = "void dirac::k_dslash_stream<0, 0, 18, false, 0, 256, false, false>(dirac::DslashArgs)"
 
 
 def fake_record(tmp_path, monkeypatch, sha="abc"):

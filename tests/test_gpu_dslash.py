@@ -353,17 +353,25 @@ def test_stream_kernel_parity(dims, tile, tc, prec, link, tol, dagger):
     f = wilson.dslash_dagger if dagger else wilson.dslash
     ref = f(lowprec.store_links(U, prec, link), lowprec.store(psi, prec), m)
     # remap bits: XCD order, t-chunks fastest, odd chunks walking down in t,
-    # and in float64 loads one direction ahead; float64 tiles stop at 256
+    # and in float64 loads one direction ahead and face spinors one slice
+    # ahead (tiles at least 2 deep in y and z); float64 tiles stop at 256
     # columns (two slice buffers of 512 exceed the LDS)
     if prec == "f64" and dims[0] * tile[0] * tile[1] > 256:
         with pytest.raises(abi.DiracError):
             op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc)
         return
-    for remap in range(16 if prec == "f64" else 8):
+    got = {}
+    for remap in range(32 if prec == "f64" else 8):
+        if remap & 16 and min(tile) < 2:
+            with pytest.raises(abi.DiracError):
+                op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc, xcd_remap=remap)
+            continue
         op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc, xcd_remap=remap)
         assert op.launch_config()["lds"] == 1
-        got = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
-        assert rel_inf(got, ref) <= tol, (remap,)
+        got[remap] = host(op.unpack_spinor(op.apply(Ui, pi, dagger=dagger)))
+        assert rel_inf(got[remap], ref) <= tol, (remap,)
+        if remap & 16:  # the same arithmetic, only the loads move
+            assert np.array_equal(got[remap], got[remap - 16]), (remap,)
 
 
 @pytest.mark.parametrize("prec,eps", [("f16s", 2.0 ** -11), ("bf16s", 2.0 ** -8)])
