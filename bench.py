@@ -388,10 +388,12 @@ def bench_multi_rhs(torch, D, steps, warmup):
         "frac": round(b12 / (ms12 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "GFLOP/s": round(12 * FLOPS_PER_SITE * V / (ms12 * 1e-3) / 1e9, 1),
         "vs_12_single_ms": round(12 * ms1, 4), "launch": cfg12, "single_launch": cfg1}
+    log("  batched CG, 12 sources (F32 mixed, float64)")
     out["cg_24x24x24x48_m0.05_12_point_sources"] = {
         "batched_f32_mixed": cg_time_multi(torch, D, dims, U, src, 0.05, "f32"),
         "batched_f64": cg_time_multi(torch, D, dims, U, src, 0.05, "f64"),
     }
+    log("  twelve single float64 solves")
     seq = 0.0
     iters = []
     for k in range(12):
@@ -402,6 +404,7 @@ def bench_multi_rhs(torch, D, steps, warmup):
     out["cg_24x24x24x48_m0.05_12_point_sources"]["sequential_f64_iters_max"] = max(iters)
     # the propagator D x = b for the 12 sources: even-odd Schur solves against
     # CG on the normal equations of D (batched, all sources at once)
+    log("  D x = b for the 12 sources")
     out["solve_Dx=b_24x24x24x48_m0.05_12_point_sources"] = {
         m: solve_d_time(torch, D, dims, U, src, 0.05, m) for m in ("ddagd_f32", "eo_f64", "eo_f32", "eo_f16s")}
     return out

@@ -378,12 +378,13 @@ typedef struct dirac_launch {
 } dirac_launch;
 
 /* Time every launch candidate above that fits this op on the given buffers
- * with HIP events and remember the fastest for every later call with the
- * same (device, geometry, precision, links, nrhs).  chi_int is overwritten.
- * Synchronises the stream.  If the environment variable DIRAC_TUNE_CACHE
- * names a file, results are appended there and read back by later
- * processes.  With DIRAC_TUNE_VERBOSE set (not "0") every candidate's time
- * is printed to stderr. */
+ * with HIP events (each on two launches, then the 16 fastest again on
+ * enough launches for about 2 ms) and remember the fastest for every later
+ * call with the same (device, geometry, precision, links, nrhs).  chi_int
+ * is overwritten.  Synchronises the stream.  If the environment variable
+ * DIRAC_TUNE_CACHE names a file, results are appended there and read back
+ * by later processes.  With DIRAC_TUNE_VERBOSE set (not "0") the final
+ * timings are printed to stderr. */
 int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, void* chi_int,
                    void* stream);
 

@@ -813,8 +813,9 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
   CHECK(hip_status(hipEventCreate(&e0), "event"));
   CHECK(hip_status(hipEventCreate(&e1), "event"));
   DslashArgs a = dslash_args(o, U_int, psi_int, chi_int);
-  // Enough launches to be well above the timer resolution.
-  const double est_us = std::max(5.0, o.V * 1e-4);
+  // Enough launches to be well above the timer resolution: about 2 ms per
+  // candidate in the final timing, from a rough 0.1 ns per site and source.
+  const double est_us = std::max(5.0, (double)o.V * o.nrhs * 1e-4);
   const int reps = (int)std::min(200.0, std::max(5.0, 2000.0 / est_us));
   std::vector<LaunchCfg> cands;
   for (int S : {64, 128, 256})
@@ -837,24 +838,43 @@ int dirac_autotune(const dirac_op* op, const void* U_int, const void* psi_int, v
         c.nt = nt;
         cands.push_back(c);
       }
-  LaunchCfg best{};
-  float best_ms = 1e30f;
   const char* verbose_env = std::getenv("DIRAC_TUNE_VERBOSE");
   const bool verbose = verbose_env != nullptr && *verbose_env && *verbose_env != '0';
   int rc = DIRAC_OK;
-  for (const LaunchCfg& c : cands) {
-    rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
-    if (rc != DIRAC_OK) break;
-    rc = hip_status(hipEventRecord(e0, st), "event record");
-    for (int k = 0; k < reps && rc == DIRAC_OK; ++k) rc = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
-    if (rc == DIRAC_OK) rc = hip_status(hipEventRecord(e1, st), "event record");
-    if (rc == DIRAC_OK) rc = hip_status(hipEventSynchronize(e1), "event sync");
-    if (rc != DIRAC_OK) break;
+  // average ms of n launches of c after one untimed launch
+  auto time_cfg = [&](const LaunchCfg& c, int n, float& ms) {
+    int r = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
+    if (r == DIRAC_OK) r = hip_status(hipEventRecord(e0, st), "event record");
+    for (int k = 0; k < n && r == DIRAC_OK; ++k) r = run_dslash(o.prec, o.prec, o.link, 0, kEpiStore, c, a, st);
+    if (r == DIRAC_OK) r = hip_status(hipEventRecord(e1, st), "event record");
+    if (r == DIRAC_OK) r = hip_status(hipEventSynchronize(e1), "event sync");
+    ms = 0.f;
+    if (r == DIRAC_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)n;
+    return r;
+  };
+  // Screen every candidate on two launches, then time the fastest kKeep on
+  // `reps` launches each and take the best of those.
+  constexpr size_t kKeep = 16;
+  std::vector<std::pair<float, size_t>> screen;
+  screen.reserve(cands.size());
+  for (size_t ci = 0; ci < cands.size() && rc == DIRAC_OK; ++ci) {
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
+    rc = time_cfg(cands[ci], 2, ms);
+    if (rc == DIRAC_OK) screen.emplace_back(ms, ci);
+  }
+  std::sort(screen.begin(), screen.end());
+  if (screen.size() > kKeep) screen.resize(kKeep);
+  LaunchCfg best{};
+  float best_ms = 1e30f;
+  for (size_t si = 0; si < screen.size() && rc == DIRAC_OK; ++si) {
+    const LaunchCfg& c = cands[screen[si].second];
+    float ms = 0.f;
+    rc = time_cfg(c, reps, ms);
+    if (rc != DIRAC_OK) break;
     if (verbose)
       std::fprintf(stderr, "dirac_autotune %s: S %d R %d remap %d lds %d nt %d tile %d x %d t_chunk %d: %.4f ms\n",
-                   cfg_key(o).c_str(), c.S, c.R, c.remap, c.lds, c.nt, c.sy, c.sz, c.tc, ms / reps);
+                   cfg_key(o).c_str(), c.S, c.R, c.remap, c.lds, c.nt, c.sy, c.sz, c.tc, ms);
     if (ms < best_ms) {
       best_ms = ms;
       best = c;
