@@ -312,20 +312,22 @@ def test_cg_with_split_kernels(inner, R):
 
 
 @pytest.mark.parametrize("tile", [(4, 4), (8, 4)])
-@pytest.mark.parametrize("remap", [1, 7])
+@pytest.mark.parametrize("remap", [1, 7, 17, 23])
 @pytest.mark.parametrize("inner", ["f64", "f32", "f16s"])
 def test_cg_with_stream_kernels(inner, remap, tile):
     # the t-streaming Dslash with its norm and residual-update epilogues
     # (remap 7: t-chunks fastest and odd chunks walking down in t), in blocks
-    # of 256 and 512 columns (float64: 256, with loads one direction ahead)
+    # of 256 and 512 columns (float64: 256, with loads one direction ahead;
+    # flags 17, 23: float64 face spinors one slice ahead, the 32- and 16-bit
+    # operators taking the low three bits)
     dims = (16, 8, 4, 8)
     U, eta = inputs(dims, "exp", seed=11)
     m = 0.1
     for prec in ("f64", "f32", "f16s"):
         ty, tz = (4, 4) if prec == "f64" else tile  # float64 tiles stop at 256 columns
         pipe = 8 if prec == "f64" and tile == (8, 4) else 0  # float64: loads one direction ahead
-        D.Operator(dims, m, prec, 12).set_launch_config(lds=1, tile_y=ty, tile_z=tz, t_chunk=3,
-                                                        xcd_remap=remap + pipe)
+        flags = remap + pipe if prec == "f64" else remap & 7
+        D.Operator(dims, m, prec, 12).set_launch_config(lds=1, tile_y=ty, tile_z=tz, t_chunk=3, xcd_remap=flags)
     x, st = solve(U, eta, m, link=12, inner=inner)
     assert st[0]["status"] == abi.OK
     assert true_res(U, eta, x, m) < 1e-10
