@@ -284,12 +284,16 @@ def schur_bytes(prec, link):
     return 2 * link_b + 5 * half
 
 
-def time_schur(torch, D, dims, prec, link, U, psi, steps, m_q):
+def time_schur(torch, D, dims, prec, link, U, psi, steps, m_q, tune=True):
     """Average ms of one D_hat application (rotating input copies past the
-    last-level cache)."""
+    last-level cache), with the operator autotuned first as a solve does: a
+    streaming launch makes its hops the streaming ones where the tile suits
+    them (float64 and float32)."""
     op = D.Operator(dims, m_q, prec, link)
     Ui = op.pack_gauge(torch.from_numpy(U).cuda())
     pi = op.pack_spinor(torch.from_numpy(psi).cuda())
+    if tune:
+        tune_for_solve(op, Ui, pi)
     per_set = op.gauge_bytes() + 2 * op.spinor_bytes()
     copies = max(1, min(8, math.ceil(2 * LLC_BYTES / per_set) + 1))
     sets = [(Ui, pi, op.empty_spinor())] + [(Ui.clone(), pi.clone(), op.empty_spinor()) for _ in range(copies - 1)]
@@ -302,8 +306,11 @@ def time_schur(torch, D, dims, prec, link, U, psi, steps, m_q):
             op.schur(u, p, out=c)
     ms = t.ms / steps
     b = schur_bytes(prec, link) * int(np.prod(dims))
+    cfg = op.launch_config()
+    stream = bool(cfg["lds"]) and prec in ("f64", "f32") and dims[0] // 2 * cfg["tile_y"] * cfg["tile_z"] >= 32
     return {"ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1),
-            "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "hop": "stream" if stream else "site",
+            "launch": cfg}
 
 
 def _d_residuals(torch, op, Ui, b_int, x_int):

@@ -481,14 +481,15 @@ int dirac_schur_apply(const dirac_op* op, const void* U_int, const void* in_int,
   a.par = 1;
   a.hop_c = 1.0;
   a.mass4 = 0.0;
-  CHECK(run_hop(o.prec, o.link, dag, kEpiStore, a, st));
+  const LaunchCfg cfg = launch_cfg(o);
+  CHECK(run_hop(o.prec, o.link, dag, kEpiStore, a, cfg, st));
   a = dslash_args(o, U_int, out_int, out_int);
   a.par = 0;
   a.ctr = (const char*)in_int;
   a.ctr_stride = o.field_stride;
   a.mass4 = A;
   a.hop_c = -1.0 / A;
-  return run_hop(o.prec, o.link, dag, kEpiStore, a, st);
+  return run_hop(o.prec, o.link, dag, kEpiStore, a, cfg, st);
 }
 
 int64_t dirac_field_dot_workspace_bytes(const dirac_op* op) {

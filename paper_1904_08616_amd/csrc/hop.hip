@@ -18,8 +18,11 @@
 // formats).
 //
 // One thread per output site and right-hand side (the per-site stencil's
-// hop code); the grid covers one parity only.
+// hop code); the grid covers one parity only.  When the operator's launch
+// configuration is the t-streaming one and its tile suits the hop (float64
+// and float32), the streaming form of hop_stream.h runs instead.
 #include "lib.h"
+#include "hop_stream.h"
 
 namespace dirac {
 
@@ -125,16 +128,41 @@ hipError_t hop_dispatch(int dag, int epi, const DslashArgs& a, hipStream_t st) {
   return launch_hop<P, PS, LK, false, kEpiSubNorm>(a, st);
 }
 
+template <int P, int LK>
+hipError_t hop_stream_dispatch(int dag, int epi, const DslashArgs& a, hipStream_t st) {
+  if (dag) {
+    if (epi == kEpiStore) return launch_hop_stream<P, P, LK, true, kEpiStore>(a, st);
+    if (epi == kEpiStoreNorm) return launch_hop_stream<P, P, LK, true, kEpiStoreNorm>(a, st);
+    return launch_hop_stream<P, P, LK, true, kEpiSubNorm>(a, st);
+  }
+  if (epi == kEpiStore) return launch_hop_stream<P, P, LK, false, kEpiStore>(a, st);
+  if (epi == kEpiStoreNorm) return launch_hop_stream<P, P, LK, false, kEpiStoreNorm>(a, st);
+  return launch_hop_stream<P, P, LK, false, kEpiSubNorm>(a, st);
+}
+
 }  // namespace
 
 int hop_partials(const Geom& g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
-int run_hop(int prec, int link, int dag, int epi, DslashArgs a, hipStream_t st) {
+int run_hop(int prec, int link, int dag, int epi, DslashArgs a, const LaunchCfg& c, hipStream_t st) {
   if (a.par != 0 && a.par != 1) return set_error(DIRAC_EINVAL, "half-lattice hop: parity must be 0 or 1");
   if (epi != kEpiStore && epi != kEpiStoreNorm && epi != kEpiSubNorm)
     return set_error(DIRAC_EINVAL, "half-lattice hop: unknown epilogue %d", epi);
-  a.remap = 1;
   hipError_t e;
+  if (c.lds && hop_stream_fits(a.g, c.sy, c.sz, c.tc, prec)) {
+    // the operator's streaming tile, in XCD-contiguous order (t-chunks
+    // fastest, which suits some D launches, made the hop slower)
+    a.sy = c.sy;
+    a.sz = c.sz;
+    a.tc = hop_stream_chunk(c.tc);
+    a.remap = kStreamXcd;
+    if (prec == DIRAC_F64 && link == 18) e = hop_stream_dispatch<DIRAC_F64, 18>(dag, epi, a, st);
+    else if (prec == DIRAC_F64 && link == 12) e = hop_stream_dispatch<DIRAC_F64, 12>(dag, epi, a, st);
+    else if (prec == DIRAC_F32 && link == 18) e = hop_stream_dispatch<DIRAC_F32, 18>(dag, epi, a, st);
+    else e = hop_stream_dispatch<DIRAC_F32, 12>(dag, epi, a, st);
+    return hip_status(e, "half-lattice hop launch");
+  }
+  a.remap = 1;
   if (prec == DIRAC_F64 && link == 18) e = hop_dispatch<DIRAC_F64, 18>(dag, epi, a, st);
   else if (prec == DIRAC_F64 && link == 12) e = hop_dispatch<DIRAC_F64, 12>(dag, epi, a, st);
   else if (prec == DIRAC_F32 && link == 18) e = hop_dispatch<DIRAC_F32, 18>(dag, epi, a, st);

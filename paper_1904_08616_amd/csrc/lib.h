@@ -56,9 +56,11 @@ DslashArgs dslash_args(const OpInfo& o, const void* U, const void* in, void* out
 
 // Half-lattice hop of the even-odd form (hop.hip): on the sites of parity
 // a.par, out = a.mass4 * ctr + a.hop_c * (K in) with the epilogue `epi`;
-// F64 and F32 with either link storage.  hop_partials: reduction partials
-// per right-hand side of one launch.
-int run_hop(int prec, int link, int dag, int epi, DslashArgs a, hipStream_t st);
+// F64 and F32 with either link storage.  A streaming configuration c (lds)
+// whose tile suits the hop selects its t-streaming form.  hop_partials:
+// reduction partials per right-hand side of one per-site launch (the
+// streaming form needs fewer).
+int run_hop(int prec, int link, int dag, int epi, DslashArgs a, const LaunchCfg& c, hipStream_t st);
 int hop_partials(const Geom& g);
 
 // CG iterations of every right-hand side of op in one launch (cg_small.hip):

@@ -152,7 +152,7 @@ int hop(const Ctx& c, const OpInfo& o, const void* U, const void* in, const void
     a.out_stride = d.stride;
     a.src_stride = d.stride;
   }
-  return run_hop(o.prec, o.link, dag, epi, a, c.st);
+  return run_hop(o.prec, o.link, dag, epi, a, launch_cfg(o), c.st);
 }
 
 // t = D in (store + |t|^2 into `kind`), for precision op o.  Even-odd form:

@@ -54,6 +54,78 @@ def test_schur_apply_vs_oracle(dims, kind, prec, link, tol, dagger):
         assert err <= tol, (k, err)
 
 
+HOP_STREAM_CASES = [
+    # dims, (tile_y, tile_z), t_chunk: the hop's block holds (X / 2) * tile_y * tile_z column pairs
+    ((16, 8, 8, 6), (4, 2), 4),    # 64 pairs in a block of 128; faces in y and z; ragged last chunk
+    ((16, 8, 8, 6), (8, 4), 3),    # 256 pairs: a tile covering y (periodic inside the tile)
+    ((12, 6, 4, 10), (3, 2), 10),  # 36 pairs (6 per row); one chunk covers t
+    ((12, 6, 4, 10), (6, 4), 1),   # 144 pairs: one tile covers y and z; one slice per block
+    ((2, 8, 4, 6), (8, 4), 2),     # one pair per row: both x neighbours in the same pair
+]
+
+
+@pytest.mark.parametrize("dims,tile,tc", HOP_STREAM_CASES)
+@pytest.mark.parametrize("prec,link,tol", [("f64", 18, 1e-13), ("f64", 12, 1e-13), ("f32", 18, 5e-6),
+                                           ("f32", 12, 5e-6)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_apply_streaming_hop_vs_oracle(dims, tile, tc, prec, link, tol, dagger):
+    # the t-streaming hop (taken when the operator's launch is the streaming
+    # one and its tile holds at least 32 column pairs; it walks the launch's
+    # t_chunk, at most 8 slices) against the oracle and the per-site hop, for
+    # two sources, whatever the launch's order flags
+    if prec == "f64" and dims[0] * tile[0] * tile[1] > 256:
+        pytest.skip("the float64 streaming D takes at most 256 columns")
+    U, psi = inputs(dims, "haar", seed=8, nrhs=2)
+    m = 0.07
+    op = D.Operator(dims, m, prec, link, 2)
+    Ui = op.pack_gauge(cuda(U))
+    pi = op.pack_spinor(cuda(psi))
+    op.set_launch_config()  # the per-site kernels
+    site = host(op.unpack_spinor(op.schur(Ui, pi, dagger=dagger)))
+    Ur = lowprec.store_links(U, prec)
+    refs = [evenodd.schur(Ur, lowprec.store(evenodd.restrict(psi[k], 0), prec), m, dagger=dagger) for k in range(2)]
+    for remap in (0, 1, 3):
+        op.set_launch_config(lds=1, tile_y=tile[0], tile_z=tile[1], t_chunk=tc, xcd_remap=remap)
+        got = host(op.unpack_spinor(op.schur(Ui, pi, dagger=dagger)))
+        for k in range(2):
+            e = evenodd.restrict(got[k], 0)
+            assert rel_inf(e, refs[k]) <= tol, (remap, k)
+            assert rel_inf(e, evenodd.restrict(site[k], 0)) <= tol, (remap, k)
+
+
+def test_streaming_hop_needs_32_pairs():
+    # a streaming tile of 32 columns is 16 column pairs: the hop keeps the
+    # per-site kernel (bitwise its result) while the full D streams
+    dims = (8, 4, 4, 6)
+    U, psi = inputs(dims, "haar", seed=9)
+    m = 0.1
+    op = D.Operator(dims, m, "f64", 18)
+    Ui, pi = op.pack_gauge(cuda(U)), op.pack_spinor(cuda(psi))
+    op.set_launch_config()
+    site = host(op.unpack_spinor(op.schur(Ui, pi)))
+    op.set_launch_config(lds=1, tile_y=2, tile_z=2, t_chunk=2)
+    assert np.array_equal(host(op.unpack_spinor(op.schur(Ui, pi))), site)
+
+
+@pytest.mark.parametrize("inner,link", [("f64", 18), ("f64", 12), ("f32", 12)])
+def test_solve_with_streaming_hops(inner, link):
+    # D x = b through the even-odd form with every hop in its streaming form
+    dims = (16, 8, 8, 16)
+    U, b = inputs(dims, "exp", seed=15)
+    m = 0.05
+    for prec, lk in (("f64", link), ("f32", link)):
+        D.Operator(dims, m, prec, lk).set_launch_config(lds=1, tile_y=4, tile_z=4, t_chunk=4, xcd_remap=1)
+    try:
+        x, st = solve_eo(U, b, m, link=link, inner=inner)
+    finally:
+        for prec, lk in (("f64", link), ("f32", link)):
+            D.Operator(dims, m, prec, lk).set_launch_config()
+    assert st[0]["status"] == abi.OK, st
+    r = d_res(U, b, x, m)
+    assert r < 1e-10
+    assert abs(st[0]["true_rel_res"] - r) <= 0.05 * r
+
+
 def test_schur_reads_only_the_even_plane():
     # NaN on every odd site of the input leaves the even result untouched
     dims = (8, 4, 6, 8)
