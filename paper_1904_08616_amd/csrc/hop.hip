@@ -149,11 +149,14 @@ int run_hop(int prec, int link, int dag, int epi, DslashArgs a, const LaunchCfg&
   if (epi != kEpiStore && epi != kEpiStoreNorm && epi != kEpiSubNorm)
     return set_error(DIRAC_EINVAL, "half-lattice hop: unknown epilogue %d", epi);
   hipError_t e;
-  if (c.lds && hop_stream_fits(a.g, c.sy, c.sz, c.tc, prec)) {
-    // the operator's streaming tile, in XCD-contiguous order (t-chunks
-    // fastest, which suits some D launches, made the hop slower)
-    a.sy = c.sy;
-    a.sz = c.sz;
+  int sy = c.sy, sz = c.sz;
+  if (c.lds) hop_stream_tile(a.g, prec, sy, sz);
+  if (c.lds && hop_stream_fits(a.g, sy, sz, c.tc, prec)) {
+    // the operator's streaming tile grown to fill the hop's block, in
+    // XCD-contiguous order (t-chunks fastest, which suits some D launches,
+    // made the hop slower)
+    a.sy = sy;
+    a.sz = sz;
     a.tc = hop_stream_chunk(c.tc);
     a.remap = kStreamXcd;
     if (prec == DIRAC_F64 && link == 18) e = hop_stream_dispatch<DIRAC_F64, 18>(dag, epi, a, st);

@@ -41,6 +41,22 @@ inline int hop_stream_block(const Geom& g, int sy, int sz) {
   const int n = hop_stream_threads(g, sy, sz);
   return n <= 128 ? 128 : (n <= 256 ? 256 : 512);
 }
+// The hop's tile, from the launch's: a tile of X * tile_y * tile_z columns
+// has half as many column pairs, so it is doubled in z, else in y (while it
+// divides the lattice and fits the largest block), until its pairs fill at
+// least 3/4 of their block.
+inline void hop_stream_tile(const Geom& g, int prec, int& sy, int& sz) {
+  const int cap = prec == DIRAC_F64 ? 256 : 512;
+  while (4 * hop_stream_threads(g, sy, sz) < 3 * hop_stream_block(g, sy, sz)) {
+    if (g.Z % (2 * sz) == 0 && hop_stream_threads(g, sy, 2 * sz) <= cap)
+      sz *= 2;
+    else if (g.Y % (2 * sy) == 0 && hop_stream_threads(g, 2 * sy, sz) <= cap)
+      sy *= 2;
+    else
+      break;
+  }
+}
+
 // The hop's t_chunk: its blocks hold half the threads and LDS of the D's, so
 // several share a CU and the hop wants more of them; it walks the D's
 // t_chunk, at most 8 slices (on 32^3 x 64 the D's 32-slice chunks fill one

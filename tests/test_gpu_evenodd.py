@@ -55,11 +55,13 @@ def test_schur_apply_vs_oracle(dims, kind, prec, link, tol, dagger):
 
 
 HOP_STREAM_CASES = [
-    # dims, (tile_y, tile_z), t_chunk: the hop's block holds (X / 2) * tile_y * tile_z column pairs
-    ((16, 8, 8, 6), (4, 2), 4),    # 64 pairs in a block of 128; faces in y and z; ragged last chunk
+    # dims, (tile_y, tile_z) of the launch, t_chunk.  The hop's tile holds (X / 2) * tile_y * tile_z
+    # column pairs and is doubled in z, then y, until they fill 3/4 of a block of 128, 256 or 512
+    # threads; it walks at most 8 slices.
+    ((16, 8, 8, 6), (4, 2), 4),    # grows to 4 x 4: 128 pairs, faces in y and z; ragged last chunk
     ((16, 8, 8, 6), (8, 4), 3),    # 256 pairs: a tile covering y (periodic inside the tile)
-    ((12, 6, 4, 10), (3, 2), 10),  # 36 pairs (6 per row); one chunk covers t
-    ((12, 6, 4, 10), (6, 4), 1),   # 144 pairs: one tile covers y and z; one slice per block
+    ((12, 6, 4, 10), (3, 2), 10),  # grows in z and y to 6 x 4 (144 pairs of 256, covering y and z); chunks of 8 and 2
+    ((12, 6, 4, 10), (6, 4), 1),   # the same tile, one slice per block
     ((2, 8, 4, 6), (8, 4), 2),     # one pair per row: both x neighbours in the same pair
 ]
 
@@ -94,16 +96,16 @@ def test_schur_apply_streaming_hop_vs_oracle(dims, tile, tc, prec, link, tol, da
 
 
 def test_streaming_hop_needs_32_pairs():
-    # a streaming tile of 32 columns is 16 column pairs: the hop keeps the
-    # per-site kernel (bitwise its result) while the full D streams
-    dims = (8, 4, 4, 6)
+    # 4 x 2 x 4 holds 16 column pairs at most: the hop keeps the per-site
+    # kernel (bitwise its result) while the full D streams (32 columns)
+    dims = (4, 2, 4, 6)
     U, psi = inputs(dims, "haar", seed=9)
     m = 0.1
     op = D.Operator(dims, m, "f64", 18)
     Ui, pi = op.pack_gauge(cuda(U)), op.pack_spinor(cuda(psi))
     op.set_launch_config()
     site = host(op.unpack_spinor(op.schur(Ui, pi)))
-    op.set_launch_config(lds=1, tile_y=2, tile_z=2, t_chunk=2)
+    op.set_launch_config(lds=1, tile_y=2, tile_z=4, t_chunk=2)
     assert np.array_equal(host(op.unpack_spinor(op.schur(Ui, pi))), site)
 
 
