@@ -259,8 +259,9 @@ int cg_solve(const dirac_op* op_hi, const void* U_hi, const void* U_lo, const vo
  * t-streaming form with the input half-slice in LDS: its tile is op's,
  * doubled in z (else y) until its (X / 2) * tile_y * tile_z column pairs
  * fill 3/4 of a block of 128 or 256 threads (float32 also 512), at least 32
- * pairs, walking at most 8 slices, in XCD-contiguous order.  Both forms
- * compute the same sums (to rounding). */
+ * pairs, walking at most 8 slices, in XCD-contiguous order, with the face
+ * spinors of the next slice requested a step ahead when the tile is at least
+ * 2 deep in y and z.  Both forms compute the same sums (to rounding). */
 
 /* out_e = D_hat in_e (dagger = 0) or D_hat^dagger in_e (dagger = 1), for
  * each of op->nrhs fields, in op's format (the 16-bit formats round the

@@ -19,7 +19,11 @@
 //     next step's output x_i is formed while U_t(x_i, t) and psi(x_i, t) are
 //     at hand and carried over.
 // Every input spinor is read from memory once per sweep (plus the tile
-// faces), every link once, as in the per-site hop.
+// faces), every link once, as in the per-site hop.  When the tile is at
+// least 2 deep in y and z (one y and one z face per thread), the face
+// spinors of the next slice are requested at the start of a step, when the
+// neighbouring tile requests the same spinors as its next slice, and carried
+// in registers (AHEAD): the second request then finds them in the L2.
 #pragma once
 
 #include "dslash_stream.h"
@@ -111,7 +115,7 @@ __device__ __forceinline__ void hop_stream_epilogue(const DslashArgs& a, int rhs
 }
 
 // One block's walk over the slices [t0, t1) of its tile (upwards).
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC>
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool AHEAD>
 __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bool act, int xh, int y, int z, int yl,
                                                 int zl, int t0, int t1, char* lds_raw, double& val) {
   using SI = SpinFmt<PI>;
@@ -140,6 +144,11 @@ __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bo
   Cx<Rl>* const wslot = lbase + 24 * NC + tid;
   constexpr bool kWtInLds = (PI == DIRAC_F64);
   const int nsteps = t1 - t0;
+  // AHEAD: the one y and one z face spinor of the output of each slice,
+  // requested a step ahead (tile_y, tile_z >= 2)
+  const bool has_fy = !(in_yp && in_ym), has_fz = !(in_zp && in_zm);
+  const int fyy = in_yp ? ym : yp, fzz = in_zp ? zm : zp;
+  Cx<Rl> fy[12], fz[12];
 
   // prologue: the input site of slice t0 into buffer 0, and the backward t
   // hop of the first output (x_o, t0) from (x_o, t0 - 1)
@@ -161,6 +170,10 @@ __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bo
 #pragma unroll
       for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
     }
+    if constexpr (AHEAD) {
+      if (has_fy) SI::load(in, Vh, P ^ 1, idx(xo, fyy, z, t0), fy);
+      if (has_fz) SI::load(in, Vh, P ^ 1, idx(xo, y, fzz, t0), fz);
+    }
   }
   __syncthreads();
 
@@ -178,6 +191,13 @@ __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bo
       // psi(x_o, tn): the forward t neighbour now, this pair's input site of slice tn next
       Cx<Rl> nxt[12];
       SI::load(in, Vh, P ^ 1, idx(xo, y, z, tn), nxt);
+      Cx<Rl> fyn[12], fzn[12];  // AHEAD: the faces of the output (x_i, tn)
+      if constexpr (AHEAD) {
+        if (s + 1 < nsteps) {
+          if (has_fy) SI::load(in, Vh, P ^ 1, idx(xi, fyy, z, tn), fyn);
+          if (has_fz) SI::load(in, Vh, P ^ 1, idx(xi, y, fzz, tn), fzn);
+        }
+      }
 
       Cx<Rl> acc[12];
 #pragma unroll
@@ -204,35 +224,51 @@ __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bo
         pin12(acc);
         // y
         LF::load(Ur, Vh, P, 1, io, u);
-        if (in_yp)
+        if (in_yp) {
           cur_s.get(tid + XH, v);
-        else
+        } else if constexpr (AHEAD) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) v[k] = fy[k];
+        } else {
           SI::load(in, Vh, P ^ 1, idx(xo, yp, z, t), v);
+        }
         hop_apply<1, DAG, true>(u, v, acc);
         {
           const int ib = idx(xo, ym, z, t);
           LF::load(Ur, Vh, P ^ 1, 1, ib, u);
-          if (in_ym)
+          if (in_ym) {
             cur_s.get(tid - XH, v);
-          else
+          } else if constexpr (AHEAD) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) v[k] = fy[k];
+          } else {
             SI::load(in, Vh, P ^ 1, ib, v);
+          }
         }
         hop_apply<1, DAG, false>(u, v, acc);
         pin12(acc);
         // z
         LF::load(Ur, Vh, P, 2, io, u);
-        if (in_zp)
+        if (in_zp) {
           cur_s.get(tid + XH * BY, v);
-        else
+        } else if constexpr (AHEAD) {
+#pragma unroll
+          for (int k = 0; k < 12; ++k) v[k] = fz[k];
+        } else {
           SI::load(in, Vh, P ^ 1, idx(xo, y, zp, t), v);
+        }
         hop_apply<2, DAG, true>(u, v, acc);
         {
           const int ib = idx(xo, y, zm, t);
           LF::load(Ur, Vh, P ^ 1, 2, ib, u);
-          if (in_zm)
+          if (in_zm) {
             cur_s.get(tid - XH * BY, v);
-          else
+          } else if constexpr (AHEAD) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) v[k] = fz[k];
+          } else {
             SI::load(in, Vh, P ^ 1, ib, v);
+          }
         }
         hop_apply<2, DAG, false>(u, v, acc);
         pin12(acc);
@@ -251,15 +287,22 @@ __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bo
           for (int k = 0; k < 6; ++k) wslot[k * NC] = Wt[k / 3][k % 3];
         }
       }
+      if constexpr (AHEAD) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          fy[k] = fyn[k];
+          fz[k] = fzn[k];
+        }
+      }
       hop_stream_epilogue<PI, PO, EPI>(a, rhs, P, io, acc, val);
     }  // act
     __syncthreads();  // slice tn complete; slice t no longer read
   }
 }
 
-template <int PI, int PO, int LK, bool DAG, int EPI, int NC>
+template <int PI, int PO, int LK, bool DAG, int EPI, int NC, bool AHEAD = false>
 __global__ void __launch_bounds__(NC)
-__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? 2 : DIRAC_STREAM_WAVES_F32)))
+__attribute__((amdgpu_waves_per_eu(PI == DIRAC_F64 ? (AHEAD ? 1 : 2) : (AHEAD ? 2 : DIRAC_STREAM_WAVES_F32))))
 k_hop_stream(DslashArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   const Geom g = a.g;
@@ -292,8 +335,8 @@ k_hop_stream(DslashArgs a) {
   if (a.gate == kGateActive) on = a.red.state[rhs].active != 0;
   double vals[1][1] = {{0.0}};
   if (on)
-    hop_stream_walk<PI, PO, LK, DAG, EPI, NC>(a, rhs, act, xh, ty * BY + yl, tz * BZ + zl, yl, zl, t0, t1, lds_raw,
-                                              vals[0][0]);
+    hop_stream_walk<PI, PO, LK, DAG, EPI, NC, AHEAD>(a, rhs, act, xh, ty * BY + yl, tz * BZ + zl, yl, zl, t0, t1,
+                                                     lds_raw, vals[0][0]);
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, l, a.ntiles);
 }
 
@@ -305,7 +348,14 @@ hipError_t launch_hop_stream(DslashArgs a, hipStream_t st) {
   a.ngroups = a.nrhs;
   const dim3 grid(a.ntiles * a.nrhs);
   const int nb = hop_stream_block(a.g, a.sy, a.sz);
-  if (nb == 128)
+  const bool ahead = a.sy >= 2 && a.sz >= 2;  // faces one slice ahead (one y and one z face per thread)
+  if (nb == 128 && ahead)
+    hipLaunchKernelGGL((k_hop_stream<PI, PO, LK, DAG, EPI, 128, true>), grid, dim3(128),
+                       (stream_lds_bytes<PI, 128>()), st, a);
+  else if (nb == 256 && ahead)
+    hipLaunchKernelGGL((k_hop_stream<PI, PO, LK, DAG, EPI, 256, true>), grid, dim3(256),
+                       (stream_lds_bytes<PI, 256>()), st, a);
+  else if (nb == 128)
     hipLaunchKernelGGL((k_hop_stream<PI, PO, LK, DAG, EPI, 128>), grid, dim3(128), (stream_lds_bytes<PI, 128>()),
                        st, a);
   else if (nb == 256)

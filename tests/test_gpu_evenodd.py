@@ -63,6 +63,7 @@ HOP_STREAM_CASES = [
     ((12, 6, 4, 10), (3, 2), 10),  # grows in z and y to 6 x 4 (144 pairs of 256, covering y and z); chunks of 8 and 2
     ((12, 6, 4, 10), (6, 4), 1),   # the same tile, one slice per block
     ((2, 8, 4, 6), (8, 4), 2),     # one pair per row: both x neighbours in the same pair
+    ((32, 8, 4, 6), (8, 1), 4),    # 128 pairs in one z plane: the walk without face spinors ahead
 ]
 
 
@@ -73,8 +74,9 @@ HOP_STREAM_CASES = [
 def test_schur_apply_streaming_hop_vs_oracle(dims, tile, tc, prec, link, tol, dagger):
     # the t-streaming hop (taken when the operator's launch is the streaming
     # one and its tile holds at least 32 column pairs; it walks the launch's
-    # t_chunk, at most 8 slices) against the oracle and the per-site hop, for
-    # two sources, whatever the launch's order flags
+    # t_chunk, at most 8 slices, with the face spinors one slice ahead when
+    # the tile is 2 deep in y and z) against the oracle and the per-site hop,
+    # for two sources, whatever the launch's order flags
     if prec == "f64" and dims[0] * tile[0] * tile[1] > 256:
         pytest.skip("the float64 streaming D takes at most 256 columns")
     U, psi = inputs(dims, "haar", seed=8, nrhs=2)
