@@ -33,10 +33,7 @@ constexpr int kHopBlock = 128;
 template <int PI, int PO, int LK, bool DAG, int EPI>
 __global__ void __launch_bounds__(kHopBlock) __attribute__((amdgpu_waves_per_eu(dslash_waves<PI, 1>())))
 k_hop(DslashArgs a) {
-  using SI = SpinFmt<PI>;
-  using SO = SpinFmt<PO>;
-  using Rl = typename SI::R;
-  using Ro = typename SO::R;
+  using Rl = typename SpinFmt<PI>::R;
   const int Vh = a.g.Vh;
   const int l = xcd_tile(blockIdx.x, a.ntiles * a.ngroups, a.remap);
   const int rhs = l % a.ngroups;  // right-hand sides of one tile side by side
@@ -59,46 +56,7 @@ k_hop(DslashArgs a) {
     hop_dir<PI, LK, DAG, 1, 1>(a, Ur, in, c, p, i, onr, acc);
     hop_dir<PI, LK, DAG, 1, 2>(a, Ur, in, c, p, i, onr, acc);
     hop_dir<PI, LK, DAG, 1, 3>(a, Ur, in, c, p, i, onr, acc);
-
-    const Rl ch = (Rl)(0.5 * a.hop_c);
-    Cx<Ro> o[12];
-    if (a.ctr != nullptr) {
-      Cx<Rl> v[12];
-      SI::load(make_rsrc(a.ctr + (size_t)rhs * a.ctr_stride, a.field_bytes), Vh, p, i, v);
-      const Rl cm = (Rl)a.mass4;
-#pragma unroll
-      for (int k = 0; k < 12; ++k)
-        o[k] = {(Ro)fma(cm, v[k].re, ch * acc[0][k].re), (Ro)fma(cm, v[k].im, ch * acc[0][k].im)};
-    } else {
-#pragma unroll
-      for (int k = 0; k < 12; ++k) o[k] = {(Ro)(ch * acc[0][k].re), (Ro)(ch * acc[0][k].im)};
-    }
-    if constexpr (EPI == kEpiStore || EPI == kEpiStoreNorm) {
-      const Rsrc orsrc = make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes);
-      Cx<Ro> q[12];  // the value as stored
-      SO::store_q(orsrc, Vh, p, i, o, q);
-      if constexpr (EPI == kEpiStoreNorm) {
-        // the exact result paired with the value as stored, as in the full
-        // stencil (the two differ for the scaled 16-bit formats)
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) s = fma((double)o[k].im, (double)q[k].im, fma((double)o[k].re, (double)q[k].re, s));
-        vals[0][0] = s;
-      }
-    } else {
-      const Ro cf = a.sub_alpha ? (Ro)a.red.state[rhs].alpha : Ro(1);
-      Cx<Ro> d[12];
-      SO::load(make_rsrc(a.src + (size_t)rhs * a.src_stride, a.out_bytes), Vh, p, i, d);
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        d[k].re = fma(-cf, o[k].re, d[k].re);
-        d[k].im = fma(-cf, o[k].im, d[k].im);
-        s = fma((double)d[k].im, (double)d[k].im, fma((double)d[k].re, (double)d[k].re, s));
-      }
-      SO::store(make_rsrc(a.out + (size_t)rhs * a.out_stride, a.out_bytes), Vh, p, i, d);
-      vals[0][0] = s;
-    }
+    hop_epilogue<PI, PO, EPI>(a, rhs, p, i, acc[0], vals[0][0]);
   }
   if constexpr (EPI != kEpiStore) block_reduce_store<1, 1>(a.red, vals, rhs, a.nrhs, tile, a.ntiles);
 }

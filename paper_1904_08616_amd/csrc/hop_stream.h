@@ -67,10 +67,13 @@ inline void hop_stream_tile(const Geom& g, int prec, int& sy, int& sz) {
 // block per CU, the hop's 8-slice ones two rounds of two).
 inline int hop_stream_chunk(int tc) { return tc < 8 ? tc : 8; }
 
-// out = mass4 * ctr + (hop_c / 2) * acc at output site (P, i), then the
-// epilogue EPI (as the per-site hop).
+// out = mass4 * ctr + (hop_c / 2) * acc at output site (P, i) of right-hand
+// side rhs, then the epilogue EPI: store, store and the norm pairing the
+// exact result with the value as stored (the two differ for the scaled
+// 16-bit formats), or dst = src - c out and |dst|^2 (c = alpha or 1).  Both
+// hop kernels end with it.
 template <int PI, int PO, int EPI>
-__device__ __forceinline__ void hop_stream_epilogue(const DslashArgs& a, int rhs, int P, int i,
+__device__ __forceinline__ void hop_epilogue(const DslashArgs& a, int rhs, int P, int i,
                                                     const Cx<typename SpinFmt<PI>::R> (&acc)[12], double& val) {
   using SI = SpinFmt<PI>;
   using SO = SpinFmt<PO>;
@@ -294,7 +297,7 @@ __device__ __forceinline__ void hop_stream_walk(const DslashArgs& a, int rhs, bo
           fz[k] = fzn[k];
         }
       }
-      hop_stream_epilogue<PI, PO, EPI>(a, rhs, P, io, acc, val);
+      hop_epilogue<PI, PO, EPI>(a, rhs, P, io, acc, val);
     }  // act
     __syncthreads();  // slice tn complete; slice t no longer read
   }
