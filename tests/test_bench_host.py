@@ -56,3 +56,30 @@ def test_cg_bound_counts_the_library_iteration():
     V = 32 ** 3 * 64
     ms, frac = bench.cg_bound((32, 32, 32, 64), dict(ms=400.0, iters=300, dslash_hi=604, dslash_lo=0), "f64", 12)
     assert abs(ms - (300 * 2688 + 2 * 1728) * V / 8e12 * 1e3) < 0.01 and abs(frac - ms / 400.0) < 1e-3
+
+
+def test_kernel_name_follows_the_launch():
+    # the name rocprofv3 reports for a launch: block size from the tile and
+    # the precision, and the float64 walk flags (8: loads one direction ahead,
+    # 16: face spinors one slice ahead); the counter record is matched on it
+    dims = bench.HEADLINE_DIMS
+    base = dict(block_sites=64, rhs_per_thread=1, nt_store=1, lds=1, t_chunk=32)
+    name = lambda prec, link, **kw: bench.kernel_name(prec, link, dict(base, **kw), dims).split(" (")[0]
+    assert name("f64", 18, xcd_remap=17, tile_y=2, tile_z=4) == "k_dslash_stream<0, 0, 18, false, 0, 256, false, true>"
+    assert name("f64", 12, xcd_remap=25, tile_y=4, tile_z=2) == "k_dslash_stream<0, 0, 12, false, 0, 256, true, true>"
+    assert name("f64", 18, xcd_remap=1, tile_y=2, tile_z=2) == "k_dslash_stream<0, 0, 18, false, 0, 128, false, false>"
+    # the 32- and 16-bit formats have no such flags: 384 columns of 24 x 4 x 4 in a 384-thread block
+    cfg = dict(base, xcd_remap=7, tile_y=4, tile_z=4)
+    assert bench.kernel_name("f32", 12, cfg, (24, 24, 24, 48)).startswith(
+        "k_dslash_stream<1, 1, 12, false, 0, 384, false, false>")
+    assert name("f16s", 12, xcd_remap=5, tile_y=4, tile_z=4) == "k_dslash_stream<2, 2, 12, false, 0, 512, false, false>"
+    assert bench.kernel_name("f64", 18, dict(base, lds=0, rhs_per_thread=2, xcd_remap=1, tile_y=1, tile_z=1,
+                                             block_sites=128), dims).startswith("k_dslash<0, 0, 18, false, 0, 2>")
+
+
+def test_schur_bytes_count_two_hops():
+    # two hops, each reading every link once and half-lattice spinors: the
+    # input and output of each, and the centre of the second
+    assert bench.schur_bytes("f64", 12) == 2 * 384 + 5 * 96 == 1248
+    assert bench.schur_bytes("f64", 18) == 2 * 576 + 5 * 96
+    assert bench.schur_bytes("f16s", 12) == 2 * 96 + 5 * 26
