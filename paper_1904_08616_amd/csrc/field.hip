@@ -1,9 +1,13 @@
 // Site-wise field kernels: layout conversion between the canonical
 // complex128 arrays and the internal even-odd formats, precision
 // conversion, and the BLAS-1 steps of the CG (Algorithm 1: inner products,
-// residual norms, vector updates).  One thread per (site, right-hand side);
-// component planes are read with coalesced 16-byte vectors.  Every
+// residual norms, vector updates).  One thread per (site, right-hand side),
+// except the float64 / float32 CG update, which is element-wise and streams
+// each field as one array; component planes are read with coalesced 16-byte
+// vectors.  Every
 // reduction accumulates in float64 and finishes in a fixed order.
+#include <type_traits>
+
 #include "field.h"
 
 namespace dirac {
@@ -319,6 +323,47 @@ k_cg_xp(Geom g, int nb, FieldDev x, FieldDev p, FieldDev r, const CgState* st) {
   SpinFmt<PP>::store(pr, g.Vh, s.p, s.i, pv);
 }
 
+// The same update when x, p and r share one unscaled format (float64 or
+// float32): it is element-wise, so it runs over each right-hand side's field
+// (or the parity plane of the even-odd vectors) as one array of 16-byte
+// elements, one per thread, consecutive threads on consecutive elements.
+// The site-wise kernel above holds 36 loads per thread in 12 planes per
+// field; this one streams three arrays and computes the same values.  AUX 2
+// marks loads and stores non-temporal (fields well beyond the last-level
+// cache, where nothing is kept for the next kernel anyway).
+template <int P, int AUX>
+__global__ void __launch_bounds__(kBlock) k_cg_xp_flat(FieldDev x, FieldDev p, FieldDev r, const CgState* st,
+                                                       uint32_t off0, uint32_t n16) {
+  const int rhs = blockIdx.y;
+  const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n16 || !st[rhs].active) return;
+  const uint32_t o = off0 + k * 16u;
+  const Rsrc xr = field_rsrc(x, rhs), pr = field_rsrc(p, rhs), rr = field_rsrc(r, rhs);
+  using T = typename std::conditional<P == DIRAC_F64, double2, float4>::type;
+  using R = typename SpinFmt<P>::R;
+  auto ld = [&](Rsrc f) { return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(f, o, 0, AUX)); };
+  T xv = ld(xr), pv = ld(pr);
+  const T rv = ld(rr);
+  const R alpha = (R)st[rhs].alpha, beta = (R)st[rhs].beta;
+  if constexpr (P == DIRAC_F64) {
+    xv.x = fma(alpha, pv.x, xv.x);
+    xv.y = fma(alpha, pv.y, xv.y);
+    pv.x = fma(beta, pv.x, rv.x);
+    pv.y = fma(beta, pv.y, rv.y);
+  } else {
+    xv.x = fma(alpha, pv.x, xv.x);
+    xv.y = fma(alpha, pv.y, xv.y);
+    xv.z = fma(alpha, pv.z, xv.z);
+    xv.w = fma(alpha, pv.w, xv.w);
+    pv.x = fma(beta, pv.x, rv.x);
+    pv.y = fma(beta, pv.y, rv.y);
+    pv.z = fma(beta, pv.z, rv.z);
+    pv.w = fma(beta, pv.w, rv.w);
+  }
+  bst<AUX>(xr, o, 0u, xv);
+  bst<AUX>(pr, o, 0u, pv);
+}
+
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_zero(Geom g, int nb, FieldDev f) {
   SiteIdx s = site_idx(g, nb);
@@ -561,6 +606,31 @@ hipError_t axpby(const Geom& g, int nrhs, FieldRef x, FieldRef y, const CgState*
 
 hipError_t cg_xp_update(const Geom& g, int nrhs, FieldRef x, FieldRef p, FieldRef r, const CgState* state,
                         hipStream_t st) {
+  if (x.prec == p.prec && p.prec == r.prec && (x.prec == DIRAC_F64 || x.prec == DIRAC_F32)) {
+    // one parity plane of Vh sites, or both
+    const uint32_t plane = (uint32_t)g.Vh * (x.prec == DIRAC_F64 ? 192u : 96u);
+    const uint32_t off0 = g.vpar > 0 ? plane : 0u;
+    const uint32_t n16 = (g.vpar >= 0 ? plane : 2u * plane) / 16u;
+    const dim3 grid((n16 + kBlock - 1) / kBlock, nrhs);
+    // non-temporal when the five vectors of a CG iteration exceed the 256 MiB last-level cache
+    const bool nt = 5.0 * (double)n16 * 16.0 * nrhs > 256.0 * (1 << 20);
+    if (x.prec == DIRAC_F64) {
+      if (nt)
+        hipLaunchKernelGGL((k_cg_xp_flat<DIRAC_F64, 2>), grid, dim3(kBlock), 0, st, dev(x), dev(p), dev(r), state,
+                           off0, n16);
+      else
+        hipLaunchKernelGGL((k_cg_xp_flat<DIRAC_F64, 0>), grid, dim3(kBlock), 0, st, dev(x), dev(p), dev(r), state,
+                           off0, n16);
+    } else {
+      if (nt)
+        hipLaunchKernelGGL((k_cg_xp_flat<DIRAC_F32, 2>), grid, dim3(kBlock), 0, st, dev(x), dev(p), dev(r), state,
+                           off0, n16);
+      else
+        hipLaunchKernelGGL((k_cg_xp_flat<DIRAC_F32, 0>), grid, dim3(kBlock), 0, st, dev(x), dev(p), dev(r), state,
+                           off0, n16);
+    }
+    return hipGetLastError();
+  }
   SiteGrid sg = site_grid(g, nrhs);
 #define XP(PX, PP, PR)                                                                              \
   if (x.prec == PX && p.prec == PP && r.prec == PR) {                                              \
@@ -568,8 +638,6 @@ hipError_t cg_xp_update(const Geom& g, int nrhs, FieldRef x, FieldRef p, FieldRe
                        dev(r), state);                                                             \
     return hipGetLastError();                                                                      \
   }
-  XP(DIRAC_F64, DIRAC_F64, DIRAC_F64)
-  XP(DIRAC_F32, DIRAC_F32, DIRAC_F32)
   XP(DIRAC_F32, DIRAC_F16S, DIRAC_F32)
   XP(DIRAC_F32, DIRAC_BF16S, DIRAC_F32)
 #undef XP
