@@ -364,6 +364,40 @@ __global__ void __launch_bounds__(kBlock) k_cg_xp_flat(FieldDev x, FieldDev p, F
   bst<AUX>(pr, o, 0u, pv);
 }
 
+// y = a x + b y (complex a, b; from the CG state when st is given) when x
+// and y share one unscaled format: element-wise over the field (or the
+// parity plane of the even-odd vectors), the same products as k_axpby.
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_axpby_flat(FieldDev x, FieldDev y, const CgState* st, double are,
+                                                       double aim, double bre, double bim, uint32_t off0,
+                                                       uint32_t n16) {
+  const int rhs = blockIdx.y;
+  const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n16) return;
+  if (st != nullptr) {
+    are = st[rhs].coef[0];
+    aim = st[rhs].coef[1];
+    bre = st[rhs].coef[2];
+    bim = st[rhs].coef[3];
+  }
+  using R = typename SpinFmt<P>::R;
+  using T = typename std::conditional<P == DIRAC_F64, double2, float4>::type;
+  const uint32_t o = off0 + k * 16u;
+  const Rsrc xr = field_rsrc(x, rhs), yr = field_rsrc(y, rhs);
+  const T xv = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(xr, o, 0, 0));
+  T yv = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(yr, o, 0, 0));
+  const Cx<R> A = {(R)are, (R)aim}, B = {(R)bre, (R)bim};
+  if constexpr (P == DIRAC_F64) {
+    const Cx<R> w = cmadd(cmul(B, Cx<R>{yv.x, yv.y}), A, Cx<R>{xv.x, xv.y});
+    yv = make_double2(w.re, w.im);
+  } else {
+    const Cx<R> w0 = cmadd(cmul(B, Cx<R>{yv.x, yv.y}), A, Cx<R>{xv.x, xv.y});
+    const Cx<R> w1 = cmadd(cmul(B, Cx<R>{yv.z, yv.w}), A, Cx<R>{xv.z, xv.w});
+    yv = make_float4(w0.re, w0.im, w1.re, w1.im);
+  }
+  bst<0>(yr, o, 0u, yv);
+}
+
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_zero(Geom g, int nb, FieldDev f) {
   SiteIdx s = site_idx(g, nb);
@@ -595,6 +629,19 @@ static hipError_t axpby_from(const Geom& g, int nrhs, FieldRef x, FieldRef y, co
 
 hipError_t axpby(const Geom& g, int nrhs, FieldRef x, FieldRef y, const CgState* s, double ar, double ai,
                  double br, double bi, hipStream_t st) {
+  if (x.prec == y.prec && (x.prec == DIRAC_F64 || x.prec == DIRAC_F32)) {
+    const uint32_t plane = (uint32_t)g.Vh * (x.prec == DIRAC_F64 ? 192u : 96u);
+    const uint32_t off0 = g.vpar > 0 ? plane : 0u;
+    const uint32_t n16 = (g.vpar >= 0 ? plane : 2u * plane) / 16u;
+    const dim3 grid((n16 + kBlock - 1) / kBlock, nrhs);
+    if (x.prec == DIRAC_F64)
+      hipLaunchKernelGGL(k_axpby_flat<DIRAC_F64>, grid, dim3(kBlock), 0, st, dev(x), dev(y), s, ar, ai, br, bi,
+                         off0, n16);
+    else
+      hipLaunchKernelGGL(k_axpby_flat<DIRAC_F32>, grid, dim3(kBlock), 0, st, dev(x), dev(y), s, ar, ai, br, bi,
+                         off0, n16);
+    return hipGetLastError();
+  }
   switch (x.prec) {
     case DIRAC_F64: return axpby_from<DIRAC_F64>(g, nrhs, x, y, s, ar, ai, br, bi, st);
     case DIRAC_F32: return axpby_from<DIRAC_F32>(g, nrhs, x, y, s, ar, ai, br, bi, st);
